@@ -1,0 +1,559 @@
+/*
+ * CPU oracle -- TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Masui et al., arXiv:1503.00638.  Every function below is the plain
+ * definition of one step of the scheme, written for a reader to check
+ * against the paper by eye: no blocking, fusion or reordering beyond what
+ * the definition states.  Floating point is IEEE double with the default
+ * round-to-nearest-even mode; build without -ffast-math and with
+ * -ffp-contract=off.  OpenMP only distributes independent rows / blocks
+ * over threads, which is the paper's own threading model (Section 4.2,
+ * "Implementation": blocks are distributed among threads).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <omp.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- constants of the stream format and of the fixed LZ4 match rule ---- */
+#define STREAM_MAGIC 0x31475342u /* bytes "BSG1" */
+#define HEADER_BYTES 24
+#define DEFAULT_BLOCK_BYTES 8192
+#define MAX_BLOCK_BYTES 65536 /* LZ4 offsets are 16-bit */
+#define HASH_BITS 12
+#define HASH_MULT 2654435761u /* Knuth's multiplicative constant */
+#define CHUNK 64             /* candidate table is updated every 64 positions */
+#define MINMATCH 4
+#define MFLIMIT 12       /* a match may start only at p <= n - 12 */
+#define LASTLITERALS 5   /* the last 5 bytes of a block are literals */
+
+int oracle_max_threads(void) { return omp_get_max_threads(); }
+
+static int pick_threads(int nthreads) { return nthreads > 0 ? nthreads : omp_get_max_threads(); }
+
+/* ======================================================================
+ * Stage 1: noise-relative precision reduction (Section 3)
+ * ====================================================================== */
+
+/* Eq. trunc_error: g < sqrt(12 f s^2), g a power of two.  With
+ * G2 = 12 f s^2 this is g^2 < G2, i.e. the largest k with 4^k < G2
+ * (strict).  frexp gives G2 < 2^e, so any k with 2k >= e fails the test
+ * and is a safe starting point; the loop then walks down to the first k
+ * that satisfies it (at most a few steps). */
+int oracle_granularity_exponent(double G2)
+{
+    int e;
+    (void)frexp(G2, &e);
+    int k = e / 2 + 1; /* 2k >= e + 1 > e */
+    while (ldexp(1.0, 2 * k) >= G2)
+        k--;
+    return k;
+}
+
+/* Round to the nearest multiple of g = 2^k, ties to the even multiple
+ * (Section 3.2, tie-breaking footnote: IEEE round-half-even, unbiased).
+ * Evaluated in double: x * 2^-k is exact for the k range kept here, rint
+ * rounds half to even in the default mode, and the result is a float
+ * value (or overflows to +-inf, the IEEE outcome). */
+float oracle_round_to_multiple(float x, int k)
+{
+    if (isnan(x) || isinf(x))
+        return x;
+    if (k < -149) /* every float is already a multiple of 2^-149 */
+        return x;
+    if (k > 200) /* |x| < 2^128 <= g/2: nearest multiple is zero */
+        return copysignf(0.0f, x);
+    double r = rint(ldexp((double)x, -k));
+    return (float)ldexp(r, k);
+}
+
+static float round_to_noise_1(float x, double G2)
+{
+    /* No positive finite noise estimate (f = 0, a dead or negative auto,
+     * NaN): nothing is discarded. */
+    if (!(G2 > 0.0) || isinf(G2))
+        return x;
+    return oracle_round_to_multiple(x, oracle_granularity_exponent(G2));
+}
+
+int oracle_round_to_noise(const float *vis_in, float *vis_out, const float *autos,
+                          int64_t F, int64_t I, int64_t T, const int32_t *prod_map,
+                          double n_samples, double f, int nthreads)
+{
+    if (F < 0 || I < 0 || T < 0)
+        return -1;
+    if (!(n_samples > 0.0) || isinf(n_samples) || !(f >= 0.0) || isinf(f))
+        return -1;
+    const int64_t P = I * (I + 1) / 2;
+    if (F * P * T > 0 && (!vis_in || !vis_out || !autos))
+        return -1;
+    int32_t *pairs = (int32_t *)malloc((size_t)(P > 0 ? P : 1) * 2 * sizeof(int32_t));
+    if (!pairs)
+        return -1;
+    if (prod_map) {
+        for (int64_t p = 0; p < P; p++) {
+            if (prod_map[2 * p] < 0 || prod_map[2 * p] >= I || prod_map[2 * p + 1] < 0 ||
+                prod_map[2 * p + 1] >= I) {
+                free(pairs);
+                return -1;
+            }
+            pairs[2 * p] = prod_map[2 * p];
+            pairs[2 * p + 1] = prod_map[2 * p + 1];
+        }
+    } else {
+        /* upper triangle, row major: (0,0) (0,1) ... (0,I-1) (1,1) ... */
+        int64_t p = 0;
+        for (int64_t i = 0; i < I; i++)
+            for (int64_t j = i; j < I; j++) {
+                pairs[2 * p] = (int32_t)i;
+                pairs[2 * p + 1] = (int32_t)j;
+                p++;
+            }
+    }
+
+    /* Section 3.1 diagonal radiometer equation, with G2 = 12 f s^2:
+     *   i != j:  s^2 = V_ii V_jj / (2N)  ->  G2 = (V_ii V_jj) * c
+     *   i == j:  s^2 = V_ii^2 / N        ->  G2 = (V_ii V_ii) * (2c)
+     * and the imaginary part of an auto carries no noise and is left alone.
+     * The product of two floats is exact in double; only "* c" rounds. */
+    const double c = (12.0 * f) / (2.0 * n_samples);
+    const double c_auto = 2.0 * c;
+
+    const int64_t rows = F * P;
+#pragma omp parallel for num_threads(pick_threads(nthreads)) schedule(static)
+    for (int64_t row = 0; row < rows; row++) {
+        const int64_t fr = row / P, p = row % P;
+        const int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
+        const float *Ai = autos + (fr * I + i) * T;
+        const float *Aj = autos + (fr * I + j) * T;
+        for (int64_t t = 0; t < T; t++) {
+            const int64_t e = 2 * (row * T + t);
+            const float re = vis_in[e], im = vis_in[e + 1];
+            if (i != j) {
+                const double G2 = ((double)Ai[t] * (double)Aj[t]) * c;
+                vis_out[e] = round_to_noise_1(re, G2);
+                vis_out[e + 1] = round_to_noise_1(im, G2);
+            } else {
+                const double G2 = ((double)Ai[t] * (double)Ai[t]) * c_auto;
+                vis_out[e] = round_to_noise_1(re, G2);
+                vis_out[e + 1] = im;
+            }
+        }
+    }
+    free(pairs);
+    return 0;
+}
+
+/* ======================================================================
+ * Stage 2a: bit transpose within blocks (Section 4.2)
+ * ====================================================================== */
+
+int64_t oracle_block_elems(int64_t elem_size, int64_t block_size)
+{
+    if (elem_size <= 0)
+        return -1;
+    if (block_size == 0) {
+        block_size = (DEFAULT_BLOCK_BYTES / elem_size) / 8 * 8;
+        if (block_size < 8)
+            block_size = 8;
+    }
+    if (block_size < 8 || block_size % 8 != 0)
+        return -1;
+    return block_size;
+}
+
+/* n elements in blocks of nb: full blocks, then one partial block of
+ * floor(rem/8)*8 elements, then rem mod 8 = n mod 8 raw tail elements. */
+static void block_layout(int64_t n, int64_t nb, int64_t *n_full, int64_t *last_elems,
+                         int64_t *n_blocks, int64_t *tail)
+{
+    *n_full = n / nb;
+    const int64_t rem = n - *n_full * nb;
+    *last_elems = rem - rem % 8;
+    *tail = rem % 8;
+    *n_blocks = *n_full + (*last_elems > 0 ? 1 : 0);
+}
+
+/* The (nb x 8E) bit matrix of a block, rows = elements, columns = bit
+ * significance b = 8 * (byte in element) + (bit in byte, LSB first),
+ * transposed into 8E rows ("planes") of nb bits, LSB plane first, each
+ * packed LSB-first into bytes (Fig. bits: bytes unpack LSB to MSB). */
+static void bitshuffle_block(const uint8_t *in, uint8_t *out, int64_t nb, int64_t E)
+{
+    const int64_t plane_bytes = nb / 8;
+    memset(out, 0, (size_t)(nb * E));
+    for (int64_t i = 0; i < nb; i++)
+        for (int64_t b = 0; b < 8 * E; b++) {
+            const unsigned bit = (in[i * E + b / 8] >> (b % 8)) & 1u;
+            out[b * plane_bytes + i / 8] |= (uint8_t)(bit << (i % 8));
+        }
+}
+
+static void bitunshuffle_block(const uint8_t *in, uint8_t *out, int64_t nb, int64_t E)
+{
+    const int64_t plane_bytes = nb / 8;
+    memset(out, 0, (size_t)(nb * E));
+    for (int64_t i = 0; i < nb; i++)
+        for (int64_t b = 0; b < 8 * E; b++) {
+            const unsigned bit = (in[b * plane_bytes + i / 8] >> (i % 8)) & 1u;
+            out[i * E + b / 8] |= (uint8_t)(bit << (b % 8));
+        }
+}
+
+static int transpose_blocks(const uint8_t *in, uint8_t *out, int64_t n, int64_t E,
+                            int64_t block_size, int nthreads, int inverse)
+{
+    const int64_t nb = oracle_block_elems(E, block_size);
+    if (nb < 0 || n < 0)
+        return -1;
+    if (n > 0 && (!in || !out))
+        return -1;
+    int64_t n_full, last, n_blocks, tail;
+    block_layout(n, nb, &n_full, &last, &n_blocks, &tail);
+#pragma omp parallel for num_threads(pick_threads(nthreads)) schedule(static)
+    for (int64_t blk = 0; blk < n_blocks; blk++) {
+        const int64_t elems = blk < n_full ? nb : last;
+        const int64_t off = blk * nb * E;
+        if (inverse)
+            bitunshuffle_block(in + off, out + off, elems, E);
+        else
+            bitshuffle_block(in + off, out + off, elems, E);
+    }
+    if (tail)
+        memcpy(out + (n - tail) * E, in + (n - tail) * E, (size_t)(tail * E));
+    return 0;
+}
+
+int oracle_bitshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                      int64_t block_size, int nthreads)
+{
+    return transpose_blocks(in, out, n, elem_size, block_size, nthreads, 0);
+}
+
+int oracle_bitunshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                        int64_t block_size, int nthreads)
+{
+    return transpose_blocks(in, out, n, elem_size, block_size, nthreads, 1);
+}
+
+/* ======================================================================
+ * Stage 2b: LZ4 block compression with a fixed greedy rule (Section 4.2:
+ * each bit-transposed block is LZ4-compressed on its own)
+ * ====================================================================== */
+
+static uint32_t le32(const uint8_t *p)
+{
+    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) |
+           ((uint32_t)p[3] << 24);
+}
+
+static uint32_t hash4(uint32_t v) { return (uint32_t)(v * HASH_MULT) >> (32 - HASH_BITS); }
+
+/* LZ4 length field continuation: a run of 255s then one byte < 255. */
+static int put_length_ext(uint8_t *dst, int64_t *op, int64_t cap, int64_t r)
+{
+    while (r >= 255) {
+        if (*op >= cap)
+            return -2;
+        dst[(*op)++] = 255;
+        r -= 255;
+    }
+    if (*op >= cap)
+        return -2;
+    dst[(*op)++] = (uint8_t)r;
+    return 0;
+}
+
+static int put_literals(uint8_t *dst, int64_t *op, int64_t cap, const uint8_t *lit,
+                        int64_t ll, int ml_nibble)
+{
+    if (*op >= cap)
+        return -2;
+    dst[(*op)++] = (uint8_t)(((ll < 15 ? ll : 15) << 4) | ml_nibble);
+    if (ll >= 15 && put_length_ext(dst, op, cap, ll - 15))
+        return -2;
+    if (ll > cap - *op)
+        return -2;
+    memcpy(dst + *op, lit, (size_t)ll);
+    *op += ll;
+    return 0;
+}
+
+int64_t oracle_lz4_compress_block(const uint8_t *x, int64_t n, uint8_t *dst, int64_t cap)
+{
+    if (n < 0 || cap < 0 || (n > 0 && !x) || (cap > 0 && !dst) || n > MAX_BLOCK_BYTES)
+        return -1;
+
+    /* Candidates: cand(p) = the largest q <= n-4 in an earlier 64-position
+     * chunk than p with the same hash, or none.  Per chunk: every position
+     * first reads the table, then every position is written in increasing
+     * order, so the largest q of each hash value survives. */
+    const int64_t last_start = n - MFLIMIT; /* matches start at p <= n - 12 */
+    int32_t *cand = (int32_t *)malloc((size_t)(last_start >= 0 ? last_start + 1 : 1) * sizeof(int32_t));
+    int32_t table[1 << HASH_BITS];
+    if (!cand)
+        return -1;
+    for (int h = 0; h < (1 << HASH_BITS); h++)
+        table[h] = -1;
+    for (int64_t c0 = 0; c0 <= n - 4; c0 += CHUNK) {
+        const int64_t c1 = (c0 + CHUNK <= n - 3) ? c0 + CHUNK : n - 3; /* q <= n-4 */
+        for (int64_t q = c0; q < c1; q++)
+            if (q <= last_start)
+                cand[q] = table[hash4(le32(x + q))];
+        for (int64_t q = c0; q < c1; q++)
+            table[hash4(le32(x + q))] = (int32_t)q;
+    }
+
+    /* Greedy parse: a match at p needs a candidate whose first 4 bytes equal
+     * those at p; it is extended forward only (no backward extension, no
+     * lazy evaluation) while keeping the last 5 bytes as literals. */
+    int64_t op = 0, anchor = 0, p = 0;
+    while (p <= last_start) {
+        const int64_t c = cand[p];
+        if (c >= 0 && le32(x + c) == le32(x + p)) {
+            int64_t L = MINMATCH;
+            while (p + L < n - LASTLITERALS && x[c + L] == x[p + L])
+                L++;
+            const int64_t ml4 = L - MINMATCH;
+            const int64_t off = p - c;
+            if (put_literals(dst, &op, cap, x + anchor, p - anchor, ml4 < 15 ? (int)ml4 : 15) ||
+                cap - op < 2) {
+                free(cand);
+                return -2;
+            }
+            dst[op++] = (uint8_t)(off & 255);
+            dst[op++] = (uint8_t)(off >> 8);
+            if (ml4 >= 15 && put_length_ext(dst, &op, cap, ml4 - 15)) {
+                free(cand);
+                return -2;
+            }
+            p += L;
+            anchor = p;
+        } else {
+            p++;
+        }
+    }
+    free(cand);
+    if (put_literals(dst, &op, cap, x + anchor, n - anchor, 0))
+        return -2;
+    return op;
+}
+
+/* Any valid LZ4 block: sequences of (token, literal length extension,
+ * literals, 16-bit offset, match length extension); the last sequence is
+ * literals only.  A match may overlap its own output (offset < length). */
+int64_t oracle_lz4_decompress_block(const uint8_t *src, int64_t n_in, uint8_t *dst,
+                                    int64_t n_out)
+{
+    if (n_in < 0 || n_out < 0 || (n_in > 0 && !src) || (n_out > 0 && !dst))
+        return -1;
+    int64_t ip = 0, op = 0;
+    for (;;) {
+        if (ip >= n_in)
+            return -3;
+        const unsigned token = src[ip++];
+        int64_t ll = token >> 4;
+        if (ll == 15) {
+            unsigned b;
+            do {
+                if (ip >= n_in)
+                    return -3;
+                b = src[ip++];
+                ll += b;
+            } while (b == 255);
+        }
+        if (ll > n_in - ip || ll > n_out - op)
+            return -3;
+        memcpy(dst + op, src + ip, (size_t)ll);
+        ip += ll;
+        op += ll;
+        if (ip == n_in)
+            break;
+        if (n_in - ip < 2)
+            return -3;
+        const int64_t off = (int64_t)src[ip] | ((int64_t)src[ip + 1] << 8);
+        ip += 2;
+        if (off == 0 || off > op)
+            return -3;
+        int64_t ml = (token & 15) + MINMATCH;
+        if ((token & 15) == 15) {
+            unsigned b;
+            do {
+                if (ip >= n_in)
+                    return -3;
+                b = src[ip++];
+                ml += b;
+            } while (b == 255);
+        }
+        if (ml > n_out - op)
+            return -3;
+        for (int64_t i = 0; i < ml; i++) /* byte by byte: overlap replicates */
+            dst[op + i] = dst[op - off + i];
+        op += ml;
+    }
+    return op == n_out ? n_out : -3;
+}
+
+/* ======================================================================
+ * The blocked stream.  Layout (little-endian):
+ *   u32 magic "BSG1", u32 elem_size, u64 n, u32 block elements, u32 n_blocks
+ *   u64 off[n_blocks + 1]   (relative to the payload start, off[0] = 0)
+ *   LZ4 block payloads, concatenated
+ *   raw tail: the last n mod 8 elements
+ * ====================================================================== */
+
+static void put_u32(uint8_t *p, uint32_t v)
+{
+    for (int i = 0; i < 4; i++)
+        p[i] = (uint8_t)(v >> (8 * i));
+}
+static void put_u64(uint8_t *p, uint64_t v)
+{
+    for (int i = 0; i < 8; i++)
+        p[i] = (uint8_t)(v >> (8 * i));
+}
+static uint32_t get_u32(const uint8_t *p)
+{
+    uint32_t v = 0;
+    for (int i = 0; i < 4; i++)
+        v |= (uint32_t)p[i] << (8 * i);
+    return v;
+}
+static uint64_t get_u64(const uint8_t *p)
+{
+    uint64_t v = 0;
+    for (int i = 0; i < 8; i++)
+        v |= (uint64_t)p[i] << (8 * i);
+    return v;
+}
+
+static int64_t lz4_block_bound(int64_t s) { return s + s / 255 + 16; }
+
+int64_t oracle_compress_bound(int64_t n, int64_t elem_size, int64_t block_size)
+{
+    const int64_t nb = oracle_block_elems(elem_size, block_size);
+    if (nb < 0 || n < 0 || nb * elem_size > MAX_BLOCK_BYTES)
+        return -1;
+    int64_t n_full, last, n_blocks, tail;
+    block_layout(n, nb, &n_full, &last, &n_blocks, &tail);
+    int64_t bound = HEADER_BYTES + 8 * (n_blocks + 1) + tail * elem_size;
+    bound += n_full * lz4_block_bound(nb * elem_size);
+    if (last)
+        bound += lz4_block_bound(last * elem_size);
+    return bound;
+}
+
+int64_t oracle_compress(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                        int64_t block_size, int64_t cap, int nthreads)
+{
+    const int64_t bound = oracle_compress_bound(n, elem_size, block_size);
+    if (bound < 0 || (n > 0 && !in) || !out)
+        return -1;
+    const int64_t E = elem_size, nb = oracle_block_elems(E, block_size);
+    int64_t n_full, last, n_blocks, tail;
+    block_layout(n, nb, &n_full, &last, &n_blocks, &tail);
+    const int64_t slot = lz4_block_bound(nb * E);
+    uint8_t *slots = (uint8_t *)malloc((size_t)(n_blocks > 0 ? n_blocks * slot : 1));
+    int64_t *size = (int64_t *)malloc((size_t)(n_blocks + 1) * sizeof(int64_t));
+    if (!slots || !size) {
+        free(slots);
+        free(size);
+        return -1;
+    }
+    /* each block: bit transpose, then LZ4 (Section 4.2) */
+#pragma omp parallel num_threads(pick_threads(nthreads))
+    {
+        uint8_t *tmp = (uint8_t *)malloc((size_t)(nb * E));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t blk = 0; blk < n_blocks; blk++) {
+            const int64_t elems = blk < n_full ? nb : last;
+            bitshuffle_block(in + blk * nb * E, tmp, elems, E);
+            size[blk] = oracle_lz4_compress_block(tmp, elems * E, slots + blk * slot, slot);
+        }
+        free(tmp);
+    }
+    int64_t total = HEADER_BYTES + 8 * (n_blocks + 1);
+    for (int64_t blk = 0; blk < n_blocks; blk++) {
+        if (size[blk] < 0) { /* cannot happen: a slot holds the LZ4 bound */
+            free(slots);
+            free(size);
+            return -1;
+        }
+        total += size[blk];
+    }
+    total += tail * E;
+    if (total > cap) {
+        free(slots);
+        free(size);
+        return -2;
+    }
+    put_u32(out, STREAM_MAGIC);
+    put_u32(out + 4, (uint32_t)E);
+    put_u64(out + 8, (uint64_t)n);
+    put_u32(out + 16, (uint32_t)nb);
+    put_u32(out + 20, (uint32_t)n_blocks);
+    uint8_t *payload = out + HEADER_BYTES + 8 * (n_blocks + 1);
+    int64_t off = 0;
+    for (int64_t blk = 0; blk < n_blocks; blk++) {
+        put_u64(out + HEADER_BYTES + 8 * blk, (uint64_t)off);
+        memcpy(payload + off, slots + blk * slot, (size_t)size[blk]);
+        off += size[blk];
+    }
+    put_u64(out + HEADER_BYTES + 8 * n_blocks, (uint64_t)off);
+    if (tail)
+        memcpy(payload + off, in + (n - tail) * E, (size_t)(tail * E));
+    free(slots);
+    free(size);
+    return total;
+}
+
+int64_t oracle_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, int64_t n,
+                          int64_t elem_size, int64_t block_size, int nthreads)
+{
+    const int64_t nb = oracle_block_elems(elem_size, block_size);
+    if (nb < 0 || n < 0 || !in || (n > 0 && !out) || nb * elem_size > MAX_BLOCK_BYTES)
+        return -1;
+    const int64_t E = elem_size;
+    int64_t n_full, last, n_blocks, tail;
+    block_layout(n, nb, &n_full, &last, &n_blocks, &tail);
+    const int64_t table_end = HEADER_BYTES + 8 * (n_blocks + 1);
+    if (in_nbytes < table_end)
+        return -3;
+    if (get_u32(in) != STREAM_MAGIC || get_u32(in + 4) != (uint32_t)E ||
+        get_u64(in + 8) != (uint64_t)n || get_u32(in + 16) != (uint32_t)nb ||
+        get_u32(in + 20) != (uint32_t)n_blocks)
+        return -3;
+    const int64_t payload_len = in_nbytes - table_end - tail * E;
+    if (payload_len < 0 || get_u64(in + HEADER_BYTES) != 0 ||
+        get_u64(in + HEADER_BYTES + 8 * n_blocks) != (uint64_t)payload_len)
+        return -3;
+    for (int64_t blk = 0; blk < n_blocks; blk++)
+        if (get_u64(in + HEADER_BYTES + 8 * (blk + 1)) < get_u64(in + HEADER_BYTES + 8 * blk))
+            return -3;
+    const uint8_t *payload = in + table_end;
+    int bad = 0;
+#pragma omp parallel num_threads(pick_threads(nthreads))
+    {
+        uint8_t *tmp = (uint8_t *)malloc((size_t)(nb * E));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t blk = 0; blk < n_blocks; blk++) {
+            const int64_t elems = blk < n_full ? nb : last;
+            const int64_t o0 = (int64_t)get_u64(in + HEADER_BYTES + 8 * blk);
+            const int64_t o1 = (int64_t)get_u64(in + HEADER_BYTES + 8 * (blk + 1));
+            if (oracle_lz4_decompress_block(payload + o0, o1 - o0, tmp, elems * E) != elems * E) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+            }
+            bitunshuffle_block(tmp, out + blk * nb * E, elems, E);
+        }
+        free(tmp);
+    }
+    if (bad)
+        return -3;
+    if (tail)
+        memcpy(out + (n - tail) * E, payload + payload_len, (size_t)(tail * E));
+    return 0;
+}

@@ -1,0 +1,73 @@
+/*
+ * CPU oracle for the two-stage radio-data compression scheme of
+ * Masui et al., "A compression scheme for radio data in high performance
+ * computing" (arXiv:1503.00638).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, obviously-correct
+ * statement of what the GPU path must compute.  It shares no code, header,
+ * table or helper with the GPU library.  Only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg may load it; the product path
+ * never does.
+ *
+ * All buffers are host memory owned by the caller.  Return codes:
+ *   0 (or a byte count >= 0)  success
+ *  -1  invalid argument
+ *  -2  output capacity too small
+ *  -3  corrupt or inconsistent compressed stream
+ */
+#ifndef BSHUF_ORACLE_H
+#define BSHUF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Section 3.1 (diagonal radiometer equation) and 3.2 (rounding granularity,
+ * Eq. trunc_error; ties-to-even footnote).  vis is complex64 laid out as
+ * float pairs [F][P][T][2]; autos float32 [F][I][T]; P = I(I+1)/2 with the
+ * products in upper-triangle row-major order unless prod_map ([P][2] int32
+ * (i, j) pairs) is given.  vis_out may equal vis_in.  nthreads <= 0 means
+ * the OpenMP default. */
+int oracle_round_to_noise(const float *vis_in, float *vis_out, const float *autos,
+                          int64_t F, int64_t I, int64_t T, const int32_t *prod_map,
+                          double n_samples, double f, int nthreads);
+
+/* The granularity exponent: largest integer k with 4^k < G2 (G2 > 0, finite). */
+int oracle_granularity_exponent(double G2);
+
+/* Round one float to the nearest multiple of 2^k, ties to the even multiple. */
+float oracle_round_to_multiple(float x, int k);
+
+/* Section 4.2: bit transpose of each block of block_size elements (a multiple
+ * of 8; 0 = 8192 bytes' worth); the last partial block keeps floor(rem/8)*8
+ * elements and the final n mod 8 elements are copied verbatim. */
+int oracle_bitshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                      int64_t block_size, int nthreads);
+int oracle_bitunshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                        int64_t block_size, int nthreads);
+
+/* One LZ4 block with the fixed greedy rule (hash bits 12, chunk 64).
+ * Returns the compressed size, or -2 when cap is too small. */
+int64_t oracle_lz4_compress_block(const uint8_t *src, int64_t n, uint8_t *dst, int64_t cap);
+
+/* General safe LZ4 block decoder: returns n_out when src decodes to exactly
+ * n_out bytes, -3 otherwise. */
+int64_t oracle_lz4_decompress_block(const uint8_t *src, int64_t n_in, uint8_t *dst,
+                                    int64_t n_out);
+
+/* Blocked stream (header, offsets, LZ4 payloads, raw tail). */
+int64_t oracle_block_elems(int64_t elem_size, int64_t block_size);
+int64_t oracle_compress_bound(int64_t n, int64_t elem_size, int64_t block_size);
+int64_t oracle_compress(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                        int64_t block_size, int64_t cap, int nthreads);
+int64_t oracle_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, int64_t n,
+                          int64_t elem_size, int64_t block_size, int nthreads);
+
+int oracle_max_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

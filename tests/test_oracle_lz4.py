@@ -1,0 +1,250 @@
+"""Pins for the oracle's LZ4 block codec and stream framing.
+
+Independent references: the system liblz4 (black box, public API only) as
+decoder and as encoder of blocks the oracle must decode; a brute-force
+re-statement of the fixed match rule written here (O(n^2) candidate search);
+a hand-derived closed form for an all-zero block; corruption fuzz."""
+import numpy as np
+import pytest
+
+import lz4ref
+from paper_1503_00638_amd import synth
+
+pytestmark = pytest.mark.skipif(not lz4ref.available(), reason="system liblz4 not present")
+
+HASH_BITS, CHUNK, MULT = 12, 64, 2654435761
+
+
+def le32(x, q):
+    return x[q] | (x[q + 1] << 8) | (x[q + 2] << 16) | (x[q + 3] << 24)
+
+
+def h(x, q):
+    return ((le32(x, q) * MULT) & 0xFFFFFFFF) >> (32 - HASH_BITS)
+
+
+def brute_encode(x: bytes) -> bytes:
+    """The fixed rule stated directly: cand(p) = largest q <= n-4 with
+    q // 64 < p // 64 and h(q) == h(p), found by scanning every q."""
+    n = len(x)
+
+    def cand(p):
+        best = None
+        for q in range(0, min(n - 4, (p // CHUNK) * CHUNK - 1) + 1):
+            if q // CHUNK < p // CHUNK and h(x, q) == h(x, p):
+                best = q
+        return best
+
+    out = bytearray()
+
+    def lits(a, b, mln):
+        ll = b - a
+        out.append((min(ll, 15) << 4) | mln)
+        if ll >= 15:
+            r = ll - 15
+            while r >= 255:
+                out.append(255)
+                r -= 255
+            out.append(r)
+        out.extend(x[a:b])
+
+    anchor = p = 0
+    while p <= n - 12:
+        c = cand(p)
+        if c is not None and x[c:c + 4] == x[p:p + 4]:
+            L = 4
+            while p + L < n - 5 and x[c + L] == x[p + L]:
+                L += 1
+            lits(anchor, p, min(L - 4, 15))
+            out.extend(((p - c) & 255, (p - c) >> 8))
+            if L - 4 >= 15:
+                r = L - 4 - 15
+                while r >= 255:
+                    out.append(255)
+                    r -= 255
+                out.append(r)
+            p += L
+            anchor = p
+        else:
+            p += 1
+    lits(anchor, n, 0)
+    return bytes(out)
+
+
+def structured_blocks(rng):
+    yield b""
+    yield bytes(5)
+    yield bytes(12)
+    yield bytes(13)
+    yield bytes(75)
+    yield bytes(76)
+    yield bytes(300)
+    yield rng.integers(0, 256, 300, dtype=np.uint8).tobytes()
+    yield rng.integers(0, 4, 400, dtype=np.uint8).tobytes()
+    yield (b"abcdefgh" * 60)[:450]
+    pat = rng.integers(0, 256, 70, dtype=np.uint8).tobytes()
+    yield pat * 5 + rng.integers(0, 256, 30, dtype=np.uint8).tobytes() + pat * 2
+    x = synth.gen_gauss_int32(96, 3, 1)
+    import oracle
+    yield oracle.bitshuffle(x, 4, 96).tobytes()
+
+
+def test_brute_force_rule(oracle_lib):
+    rng = np.random.default_rng(0)
+    for blk in structured_blocks(rng):
+        assert oracle_lib.lz4_compress_block(np.frombuffer(blk, np.uint8)) == brute_encode(blk), len(blk)
+
+
+def test_all_zero_closed_form(oracle_lib):
+    """Positions 0..63 have no candidate (chunk 0); p = 64 matches q = 63 at
+    offset 1 and extends to n - 5; then 5 literals close the block."""
+    for n in (76, 200, 4096, 8192, 65536):
+        got = oracle_lib.lz4_compress_block(np.zeros(n, np.uint8))
+        L = n - 5 - 64
+        exp = bytearray([0xF0 | min(L - 4, 15), 64 - 15]) + bytes(64) + bytes([1, 0])
+        if L - 4 >= 15:
+            r = L - 4 - 15
+            while r >= 255:
+                exp.append(255)
+                r -= 255
+            exp.append(r)
+        exp += bytes([0x50]) + bytes(5)
+        assert got == bytes(exp), n
+
+
+def _check_end_rules(comp: bytes, n: int):
+    seqs = lz4ref.parse_sequences(comp)
+    assert seqs[-1][1] is None
+    pos = 0
+    for lit, off, ml in seqs[:-1]:
+        pos += len(lit)
+        assert pos <= n - 12  # match start
+        assert 1 <= off <= pos
+        pos += ml
+        assert pos <= n - 5  # last five bytes are literals
+    pos += len(seqs[-1][0])
+    assert pos == n
+    assert len(seqs[-1][0]) >= min(n, 5)
+
+
+def test_liblz4_decodes_oracle_blocks(oracle_lib):
+    rng = np.random.default_rng(1)
+    blocks = list(structured_blocks(rng))
+    vis, autos = synth.gen_vis(2, 8, 64, 0)
+    r = oracle_lib.round_to_noise(vis, autos, 3.9e6, 0.01)
+    sh = oracle_lib.bitshuffle(r, 4, 2048)
+    blocks += [sh[i:i + 8192].tobytes() for i in range(0, sh.size, 8192)]
+    blocks += [oracle_lib.bitshuffle(synth.gen_walk_int16(32768, 5), 2, 32768).tobytes()]
+    blocks += [rng.integers(0, 256, 65536, dtype=np.uint8).tobytes(), bytes(65536)]
+    for blk in blocks:
+        comp = oracle_lib.lz4_compress_block(np.frombuffer(blk, np.uint8))
+        assert len(comp) <= len(blk) + len(blk) // 255 + 16
+        assert lz4ref.decompress_safe(comp, len(blk)) == blk
+        assert oracle_lib.lz4_decompress_block(comp, len(blk)) == blk
+        _check_end_rules(comp, len(blk))
+
+
+def test_oracle_decodes_liblz4_blocks(oracle_lib):
+    rng = np.random.default_rng(2)
+    for blk in list(structured_blocks(rng)) + [bytes(range(256)) * 40]:
+        if not blk:
+            continue
+        for comp in (lz4ref.compress_default(blk), lz4ref.compress_hc(blk, 9)):
+            assert oracle_lib.lz4_decompress_block(comp, len(blk)) == blk
+
+
+def test_decoder_rejects_corruption(oracle_lib):
+    rng = np.random.default_rng(3)
+    blk = oracle_lib.bitshuffle(synth.gen_gauss_int32(2048, 6, 9), 4, 2048).tobytes()
+    comp = bytearray(oracle_lib.lz4_compress_block(np.frombuffer(blk, np.uint8)))
+    import oracle
+    bad = 0
+    for trial in range(400):
+        c = bytearray(comp)
+        kind = trial % 4
+        if kind == 0:
+            i = int(rng.integers(0, len(c)))
+            c[i] ^= 1 << int(rng.integers(0, 8))
+        elif kind == 1:
+            c = c[: int(rng.integers(0, len(c)))]
+        elif kind == 2:
+            c = c + bytes([int(rng.integers(0, 256))])
+        else:
+            i = int(rng.integers(0, len(c)))
+            c[i] = 0xFF
+        try:
+            out = oracle_lib.lz4_decompress_block(bytes(c), len(blk))
+            # a flip inside literal bytes still decodes (to different data)
+            assert len(out) == len(blk)
+        except oracle.OracleError as e:
+            assert e.code == -3
+            bad += 1
+    assert bad > 100
+    # specific malformed blocks
+    for c, n in ((b"", 0), (b"\x00\x00", 1), (b"\x10a\x00\x00", 5), (b"\x10a\x02\x00", 5),
+                 (b"\x1fa\x01\x00", 400), (b"\xf0", 20), (b"\x20ab", 3)):
+        with pytest.raises(oracle.OracleError):
+            oracle_lib.lz4_decompress_block(c, n)
+
+
+STREAM_CASES = [(4, 2048, 0), (4, 2048, 2048 * 3 + 8 * 5 + 3), (2, 4096, 10001), (8, 1024, 5555),
+                (1, 8192, 8192 * 2 + 7), (16, 512, 1000), (3, 64, 999), (4, 16, 1)]
+
+
+@pytest.mark.parametrize("E,nb,n", STREAM_CASES)
+def test_stream_roundtrip_and_layout(oracle_lib, E, nb, n):
+    rng = np.random.default_rng(n)
+    data = (rng.integers(0, 16, n * E, dtype=np.uint8) * 3).astype(np.uint8)
+    s = oracle_lib.compress(data, E, nb)
+    assert s.size <= oracle_lib.compress_bound(n, E, nb)
+    hdr = s[:24]
+    assert hdr[:4].tobytes() == b"BSG1"
+    assert int(hdr[4:8].view(np.uint32)[0]) == E
+    assert int(hdr[8:16].view(np.uint64)[0]) == n
+    assert int(hdr[16:20].view(np.uint32)[0]) == nb
+    nblk = int(hdr[20:24].view(np.uint32)[0])
+    full, rem = divmod(n, nb)
+    last = rem - rem % 8
+    assert nblk == full + (last > 0)
+    off = s[24:24 + 8 * (nblk + 1)].view(np.uint64)
+    pay = s[24 + 8 * (nblk + 1):]
+    assert off[0] == 0 and np.all(np.diff(off.astype(np.int64)) > 0)
+    tail = (n % 8) * E
+    assert pay.size == int(off[-1]) + tail
+    if tail:
+        assert np.array_equal(pay[-tail:], data[-tail:])
+    sh = oracle_lib.bitshuffle(data, E, nb)
+    for b in range(nblk):
+        elems = nb if b < full else last
+        blk = sh[b * nb * E: b * nb * E + elems * E].tobytes()
+        comp = pay[int(off[b]):int(off[b + 1])].tobytes()
+        assert lz4ref.decompress_safe(comp, len(blk)) == blk
+        assert comp == oracle_lib.lz4_compress_block(np.frombuffer(blk, np.uint8))
+    assert np.array_equal(oracle_lib.decompress(s, n, E, nb), data)
+
+
+def test_stream_rejects_mismatch_and_corruption(oracle_lib):
+    import oracle
+    data = np.arange(4096, dtype=np.int32)
+    s = oracle_lib.compress(data, 4, 1024)
+    with pytest.raises(oracle.OracleError):
+        oracle_lib.decompress(s, 4096, 4, 2048)  # block size disagrees with header
+    with pytest.raises(oracle.OracleError):
+        oracle_lib.decompress(s, 4095, 4, 1024)
+    with pytest.raises(oracle.OracleError):
+        oracle_lib.decompress(s[:-1], 4096, 4, 1024)
+    t = s.copy()
+    t[24 + 8] ^= 0x40  # corrupt an offset
+    with pytest.raises(oracle.OracleError):
+        oracle_lib.decompress(t, 4096, 4, 1024)
+    with pytest.raises(oracle.OracleError):
+        oracle_lib.compress(data, 4, 65536)  # block above 64 KiB
+
+
+def test_threads_do_not_change_bytes(oracle_lib):
+    vis, autos = synth.gen_vis(4, 8, 32, 2)
+    r = oracle_lib.round_to_noise(vis, autos, 3.9e6, 0.01, nthreads=3)
+    assert np.array_equal(r.view(np.uint32), oracle_lib.round_to_noise(vis, autos, 3.9e6, 0.01, nthreads=1).view(np.uint32))
+    a = oracle_lib.compress(r, 4, 2048, nthreads=1)
+    b = oracle_lib.compress(r, 4, 2048, nthreads=5)
+    assert np.array_equal(a, b)
