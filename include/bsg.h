@@ -1,0 +1,157 @@
+/*
+ * bsg: GPU (gfx950) implementation of the two-stage compression scheme for
+ * radio visibilities of Masui et al., "A compression scheme for radio data in
+ * high performance computing", arXiv:1503.00638:
+ *
+ *   1. noise-relative precision reduction (Section 3): every visibility is
+ *      rounded to a multiple of the largest power of two g with
+ *      g^2 < 12 f s^2, s from the diagonal radiometer equation (Section 3.1);
+ *   2. Bitshuffle (Section 4.2): the bits of each fixed-size block of typed
+ *      elements are transposed (element x bit matrix -> bit planes), then each
+ *      block is compressed on its own with LZ4.
+ *
+ * Conventions for every entry point:
+ *  - Data pointers are DEVICE pointers.  The caller allocates and owns every
+ *    buffer; the library never allocates on these paths.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *    enqueues work on it and returns; results are ready when the stream is.
+ *  - The int return value reports argument and launch checks made on the host
+ *    (BSG_OK or a negative BSG_E* code).  Results that depend on the data
+ *    (compressed size, decode status) are written to caller-provided device
+ *    words.
+ *  - No global mutable state: calls on different streams may run concurrently
+ *    (the paper's thread-safety requirement, Section 2 and Section 4.2).
+ *  - block_size is counted in ELEMENTS and must be a multiple of 8; 0 selects
+ *    the default, 8192 bytes' worth of elements rounded down to a multiple of 8.
+ *    A block of n_B elements is transposed as an (n_B x 8E) bit matrix.  The
+ *    buffer is cut into floor(n / n_B) full blocks, one partial block of
+ *    floor(rem / 8) * 8 elements when that is non-zero, and a raw tail of the
+ *    last n mod 8 elements which is copied verbatim.
+ */
+#ifndef BSG_H
+#define BSG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BSG_OK 0
+#define BSG_EINVAL (-1)    /* invalid argument */
+#define BSG_ECAPACITY (-2) /* output buffer or workspace too small */
+#define BSG_ECORRUPT (-3)  /* compressed stream is corrupt or does not match */
+#define BSG_EHIP (-4)      /* a HIP runtime call failed */
+
+#define BSG_MAX_BLOCK_BYTES 65536 /* LZ4 offsets are 16-bit */
+
+/* Compressed stream layout (all little-endian):
+ *   bsg_header (24 bytes)
+ *   uint64 off[n_blocks + 1]   LZ4 block k occupies payload[off[k], off[k+1])
+ *   payload: the LZ4 blocks, concatenated, off[0] = 0
+ *   raw tail: the last (n mod 8) elements, verbatim                       */
+#define BSG_MAGIC 0x31475342u /* bytes "BSG1" */
+typedef struct bsg_header {
+    uint32_t magic;
+    uint32_t elem_size;
+    uint64_t n;          /* elements */
+    uint32_t block_elems;
+    uint32_t n_blocks;
+} bsg_header;
+
+const char *bsg_strerror(int code);
+
+/* Elements per block for a given block_size argument (0 = default), or
+ * BSG_EINVAL. Host only. */
+int64_t bsg_block_elems(int64_t elem_size, int64_t block_size);
+
+/* ---- Stage 1: precision reduction (Section 3.1, Section 3.2) ----------
+ * vis_in / vis_out: complex64 [F][P][T] (re, im float32 pairs), C order,
+ *   time fastest; vis_out may equal vis_in (in place).  8-byte aligned.
+ * autos: float32 [F][I][T], the measured auto-correlations V_ii (the real
+ *   parts of the auto products BEFORE rounding); must not overlap vis_out.
+ * P = I (I + 1) / 2 products.  prod_map: NULL for upper-triangle row-major
+ *   order ((0,0), (0,1), ..., (0,I-1), (1,1), ...), else a device int32
+ *   [P][2] table of (i, j) with 0 <= i, j < I (i == j marks an auto).
+ * n_samples: N = bandwidth x integration time (> 0).  f: the tolerated
+ *   fractional increase of the noise variance (>= 0; 0 leaves data as is).
+ * Per element: G2 = (V_ii V_jj) c for i != j and (V_ii V_ii) 2c for autos,
+ *   c = (12 f) / (2 N) in IEEE double (the product of two floats is exact);
+ *   k = the largest integer with 4^k < G2; re and im are rounded to the
+ *   nearest multiple of 2^k, ties to even; the imaginary part of an auto is
+ *   copied.  G2 not positive and finite (f = 0, a zero, negative or NaN auto)
+ *   leaves the element unchanged; NaN and Inf values pass through; the sign
+ *   of zero is kept.
+ * Errors: BSG_EINVAL for negative sizes, NULL pointers with a non-empty
+ *   array, n_samples <= 0 or f < 0 or non-finite; BSG_EHIP on launch failure.
+ *   Entries of prod_map outside [0, I) are not checked on the device. */
+int bsg_round_to_noise(const void *vis_in, void *vis_out, const float *autos, int64_t F,
+                       int64_t I, int64_t T, const int32_t *prod_map, double n_samples,
+                       double f, void *stream);
+
+/* ---- Stage 2a: bit transpose within blocks (Section 4.2) --------------
+ * in, out: n elements of elem_size bytes; must not overlap.
+ * Bit b = 8 * (byte within element) + (bit within byte, LSB = 0) of element
+ * i of a block goes to output byte  b * (n_B / 8) + i / 8,  bit i mod 8, i.e.
+ * 8E planes, least-significant plane first, each packed LSB-first.
+ * bitunshuffle is the exact inverse.
+ * Errors: BSG_EINVAL (elem_size < 1, bad block_size, n < 0, NULL). */
+int bsg_bitshuffle(const void *in, void *out, int64_t n, int64_t elem_size, int64_t block_size,
+                   void *stream);
+int bsg_bitunshuffle(const void *in, void *out, int64_t n, int64_t elem_size,
+                     int64_t block_size, void *stream);
+
+/* ---- Stage 2b: bit transpose + per-block LZ4 (Section 4.2) ------------
+ * Exact worst-case size of the compressed stream (host, no device work). */
+int64_t bsg_compress_bound(int64_t n, int64_t elem_size, int64_t block_size);
+
+/* Device workspace bytes bsg_compress_lz4 needs for these sizes. */
+int64_t bsg_compress_workspace_size(int64_t n, int64_t elem_size, int64_t block_size);
+
+/* Compress n elements into the stream format above.  Every block is
+ * bit-transposed and LZ4-encoded with one fixed, deterministic greedy rule
+ * (hash of 4 bytes, 12 bits, Knuth's multiplier 2654435761; candidate = the
+ * last earlier position with that hash in an earlier 64-position chunk; a
+ * match needs 4 equal bytes, starts at p <= len - 12, is extended forward
+ * only and keeps the last 5 bytes literal), so the output bytes are a pure
+ * function of the input.
+ * out: out_capacity bytes.  *d_out_nbytes (device int64) receives the
+ *   stream length, or BSG_ECAPACITY when it would exceed out_capacity (then
+ *   out holds nothing meaningful).  Pass out_capacity >= bsg_compress_bound
+ *   to never see that.
+ * workspace: device memory of bsg_compress_workspace_size bytes, 256-byte
+ *   aligned; workspace_bytes is its size.  Blocks above 65536 bytes are
+ *   rejected (BSG_EINVAL). */
+int bsg_compress_lz4(const void *in, void *out, int64_t n, int64_t elem_size,
+                     int64_t block_size, int64_t out_capacity, int64_t *d_out_nbytes,
+                     void *workspace, int64_t workspace_bytes, void *stream);
+
+/* The two stages fused: round_to_noise on complex64 visibilities (arguments
+ * as bsg_round_to_noise, vis_in is not modified), then bitshuffle + LZ4 of
+ * the rounded values viewed as float32 elements (elem_size 4, n = 2 F P T),
+ * without writing the rounded array.  The stream is byte-identical to
+ * bsg_round_to_noise followed by bsg_compress_lz4 with elem_size 4. */
+int bsg_round_compress_lz4(const void *vis_in, const float *autos, int64_t F, int64_t I,
+                           int64_t T, const int32_t *prod_map, double n_samples, double f,
+                           int64_t block_size, void *out, int64_t out_capacity,
+                           int64_t *d_out_nbytes, void *workspace, int64_t workspace_bytes,
+                           void *stream);
+
+/* Decompress a stream made by bsg_compress_lz4 (any valid LZ4 encoding of
+ * the blocks is accepted, not only this library's).  n, elem_size and
+ * block_size must equal the header's.  in_nbytes is the stream length.
+ * *d_status (device int32) must be 0 on entry; it stays 0 on success and
+ * receives BSG_ECORRUPT when the header, offsets or any block is invalid
+ * (bad offset, overrun, short or long output, trailing bytes).  Reads and
+ * writes stay inside in[0, in_nbytes) and out[0, n * elem_size) whatever
+ * the input holds. */
+int bsg_decompress_lz4(const void *in, int64_t in_nbytes, void *out, int64_t n,
+                       int64_t elem_size, int64_t block_size, int32_t *d_status, void *stream);
+
+/* Parse a stream header from HOST memory (no device work). */
+int bsg_read_header(const void *host_bytes, int64_t nbytes, bsg_header *hdr);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,211 @@
+"""MI355X (gfx950) implementation of the radio-data compression scheme of
+Masui et al., arXiv:1503.00638: noise-relative rounding (Section 3) and
+Bitshuffle, the blocked bit transpose plus per-block LZ4 (Section 4.2).
+
+The compute is the HIP library libbsg.so behind the C-ABI in include/bsg.h;
+this module only marshals torch device tensors (device memory and streams)
+into those calls.  Every function enqueues on the current torch stream (or
+the one given) and returns without synchronising, except the *_sync helpers.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (BSG_ECAPACITY, BSG_ECORRUPT, BSG_EHIP, BSG_EINVAL, BSG_OK, BsgError,
+                   Header)
+
+__all__ = [
+    "round_to_noise", "bitshuffle", "bitunshuffle", "compress_bound", "workspace_size",
+    "compress", "round_compress", "decompress", "block_elems", "read_header", "BsgError",
+    "compress_sync", "decompress_sync", "BSG_OK", "BSG_EINVAL", "BSG_ECAPACITY",
+    "BSG_ECORRUPT", "BSG_EHIP", "load",
+]
+
+
+def load():
+    """Load libbsg.so (raises ImportError when it is not built)."""
+    return _lib.lib()
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require_device(*ts):
+    for t in ts:
+        if t is not None:
+            if not t.is_cuda:
+                raise ValueError("bsg operates on device tensors only")
+            if not t.is_contiguous():
+                raise ValueError("bsg needs contiguous tensors")
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    return t.numel() * t.element_size()
+
+
+def block_elems(elem_size: int, block_size: int = 0) -> int:
+    r = _lib.lib().bsg_block_elems(elem_size, block_size)
+    if r < 0:
+        raise BsgError(int(r), "block_elems")
+    return int(r)
+
+
+def round_to_noise(vis: torch.Tensor, autos: torch.Tensor, n_samples: float, f: float,
+                   out: torch.Tensor | None = None, prod_map: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """vis complex64 (F, P, T), autos float32 (F, I, T) -> rounded vis
+    (out may be vis itself for in-place rounding)."""
+    _require_device(vis, autos, out, prod_map)
+    if vis.dtype != torch.complex64 or autos.dtype != torch.float32:
+        raise TypeError("vis must be complex64 and autos float32")
+    F, I, T = autos.shape
+    if tuple(vis.shape) != (F, I * (I + 1) // 2, T):
+        raise ValueError(f"vis {tuple(vis.shape)} does not match autos {tuple(autos.shape)}")
+    if out is None:
+        out = torch.empty_like(vis)
+    if prod_map is not None and (prod_map.dtype != torch.int32 or tuple(prod_map.shape) != (vis.shape[1], 2)):
+        raise ValueError("prod_map must be int32 (P, 2)")
+    _lib.check(_lib.lib().bsg_round_to_noise(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
+                                              _ptr(prod_map), float(n_samples), float(f),
+                                              _stream_ptr(stream)), "round_to_noise")
+    return out
+
+
+def _transpose(fn, x, elem_size, block_size, out, stream, what):
+    _require_device(x, out)
+    nb = _nbytes(x)
+    if nb % elem_size:
+        raise ValueError("buffer is not a whole number of elements")
+    if out is None:
+        out = torch.empty(nb, dtype=torch.uint8, device=x.device)
+    if _nbytes(out) < nb:
+        raise ValueError("output too small")
+    _lib.check(fn(_ptr(x), _ptr(out), nb // elem_size, elem_size, block_size, _stream_ptr(stream)),
+               what)
+    return out
+
+
+def bitshuffle(x: torch.Tensor, elem_size: int, block_size: int = 0,
+               out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    return _transpose(_lib.lib().bsg_bitshuffle, x, elem_size, block_size, out, stream,
+                      "bitshuffle")
+
+
+def bitunshuffle(x: torch.Tensor, elem_size: int, block_size: int = 0,
+                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    return _transpose(_lib.lib().bsg_bitunshuffle, x, elem_size, block_size, out, stream,
+                      "bitunshuffle")
+
+
+def compress_bound(n: int, elem_size: int, block_size: int = 0) -> int:
+    r = _lib.lib().bsg_compress_bound(n, elem_size, block_size)
+    if r < 0:
+        raise BsgError(int(r), "compress_bound")
+    return int(r)
+
+
+def workspace_size(n: int, elem_size: int, block_size: int = 0) -> int:
+    r = _lib.lib().bsg_compress_workspace_size(n, elem_size, block_size)
+    if r < 0:
+        raise BsgError(int(r), "workspace_size")
+    return int(r)
+
+
+def _alloc_ws(n, elem_size, block_size, device, workspace):
+    need = workspace_size(n, elem_size, block_size)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=device)
+    return workspace
+
+
+def compress(x: torch.Tensor, elem_size: int, block_size: int = 0,
+             out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+             nbytes: torch.Tensor | None = None, stream=None):
+    """Enqueue compression of x.  Returns (out, nbytes): out is a uint8 buffer
+    of compress_bound bytes (or the one given), nbytes a device int64 holding
+    the stream length (or BSG_ECAPACITY) once the stream has run."""
+    _require_device(x, out, workspace, nbytes)
+    total = _nbytes(x)
+    if total % elem_size:
+        raise ValueError("buffer is not a whole number of elements")
+    n = total // elem_size
+    if out is None:
+        out = torch.empty(compress_bound(n, elem_size, block_size), dtype=torch.uint8,
+                          device=x.device)
+    workspace = _alloc_ws(n, elem_size, block_size, x.device, workspace)
+    if nbytes is None:
+        nbytes = torch.empty(1, dtype=torch.int64, device=x.device)
+    _lib.check(_lib.lib().bsg_compress_lz4(_ptr(x), _ptr(out), n, elem_size, block_size,
+                                            _nbytes(out), _ptr(nbytes), _ptr(workspace),
+                                            _nbytes(workspace), _stream_ptr(stream)),
+               "compress_lz4")
+    return out, nbytes
+
+
+def round_compress(vis: torch.Tensor, autos: torch.Tensor, n_samples: float, f: float,
+                   block_size: int = 0, out: torch.Tensor | None = None,
+                   workspace: torch.Tensor | None = None, nbytes: torch.Tensor | None = None,
+                   prod_map: torch.Tensor | None = None, stream=None):
+    """round_to_noise fused into compress (elem_size 4); vis is not modified."""
+    _require_device(vis, autos, out, workspace, nbytes, prod_map)
+    F, I, T = autos.shape
+    n = 2 * vis.numel()
+    if out is None:
+        out = torch.empty(compress_bound(n, 4, block_size), dtype=torch.uint8, device=vis.device)
+    workspace = _alloc_ws(n, 4, block_size, vis.device, workspace)
+    if nbytes is None:
+        nbytes = torch.empty(1, dtype=torch.int64, device=vis.device)
+    _lib.check(_lib.lib().bsg_round_compress_lz4(_ptr(vis), _ptr(autos), F, I, T, _ptr(prod_map),
+                                                  float(n_samples), float(f), block_size,
+                                                  _ptr(out), _nbytes(out), _ptr(nbytes),
+                                                  _ptr(workspace), _nbytes(workspace),
+                                                  _stream_ptr(stream)), "round_compress_lz4")
+    return out, nbytes
+
+
+def decompress(stream_bytes: torch.Tensor, in_nbytes: int, n: int, elem_size: int,
+               block_size: int = 0, out: torch.Tensor | None = None,
+               status: torch.Tensor | None = None, stream=None):
+    """Enqueue decompression.  Returns (out, status): status is a device int32
+    that reads 0 on success and BSG_ECORRUPT otherwise."""
+    _require_device(stream_bytes, out, status)
+    if out is None:
+        out = torch.empty(max(n * elem_size, 1), dtype=torch.uint8, device=stream_bytes.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=stream_bytes.device)
+    _lib.check(_lib.lib().bsg_decompress_lz4(_ptr(stream_bytes), int(in_nbytes), _ptr(out), n,
+                                              elem_size, block_size, _ptr(status),
+                                              _stream_ptr(stream)), "decompress_lz4")
+    return out, status
+
+
+def compress_sync(x: torch.Tensor, elem_size: int, block_size: int = 0) -> torch.Tensor:
+    out, nb = compress(x, elem_size, block_size)
+    m = int(nb.item())
+    if m < 0:
+        raise BsgError(m, "compress_lz4")
+    return out[:m]
+
+
+def decompress_sync(s: torch.Tensor, n: int, elem_size: int, block_size: int = 0) -> torch.Tensor:
+    out, st = decompress(s, _nbytes(s), n, elem_size, block_size)
+    code = int(st.item())
+    if code != 0:
+        raise BsgError(code, "decompress_lz4")
+    return out[: n * elem_size]
+
+
+def read_header(host_bytes: bytes) -> Header:
+    h = Header()
+    buf = ctypes.create_string_buffer(bytes(host_bytes[:24]), 24)
+    _lib.check(_lib.lib().bsg_read_header(buf, len(host_bytes), ctypes.byref(h)), "read_header")
+    return h

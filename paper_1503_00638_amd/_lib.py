@@ -1,0 +1,85 @@
+"""ctypes binding of libbsg.so (the C-ABI declared in include/bsg.h).
+
+Argument marshalling only: every step runs in the HIP library.  Loading
+fails loudly when the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbsg.so")
+
+BSG_OK = 0
+BSG_EINVAL = -1
+BSG_ECAPACITY = -2
+BSG_ECORRUPT = -3
+BSG_EHIP = -4
+MAGIC = 0x31475342
+
+EXPORTS = (
+    "bsg_strerror", "bsg_block_elems", "bsg_round_to_noise", "bsg_bitshuffle",
+    "bsg_bitunshuffle", "bsg_compress_bound", "bsg_compress_workspace_size",
+    "bsg_compress_lz4", "bsg_round_compress_lz4", "bsg_decompress_lz4", "bsg_read_header",
+)
+
+
+class Header(ctypes.Structure):
+    _fields_ = [("magic", ctypes.c_uint32), ("elem_size", ctypes.c_uint32),
+                ("n", ctypes.c_uint64), ("block_elems", ctypes.c_uint32),
+                ("n_blocks", ctypes.c_uint32)]
+
+
+class BsgError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = _lib().bsg_strerror(code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})")
+        self.code = code
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1503_00638_amd.build` "
+                "(or __graft_entry__.build()); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        L.bsg_strerror.argtypes = [i32]
+        L.bsg_strerror.restype = ctypes.c_char_p
+        L.bsg_block_elems.argtypes = [i64, i64]
+        L.bsg_block_elems.restype = i64
+        L.bsg_round_to_noise.argtypes = [vp, vp, vp, i64, i64, i64, vp, dbl, dbl, vp]
+        L.bsg_round_to_noise.restype = i32
+        for f in (L.bsg_bitshuffle, L.bsg_bitunshuffle):
+            f.argtypes = [vp, vp, i64, i64, i64, vp]
+            f.restype = i32
+        L.bsg_compress_bound.argtypes = [i64, i64, i64]
+        L.bsg_compress_bound.restype = i64
+        L.bsg_compress_workspace_size.argtypes = [i64, i64, i64]
+        L.bsg_compress_workspace_size.restype = i64
+        L.bsg_compress_lz4.argtypes = [vp, vp, i64, i64, i64, i64, vp, vp, i64, vp]
+        L.bsg_compress_lz4.restype = i32
+        L.bsg_round_compress_lz4.argtypes = [vp, vp, i64, i64, i64, vp, dbl, dbl, i64, vp, i64,
+                                             vp, vp, i64, vp]
+        L.bsg_round_compress_lz4.restype = i32
+        L.bsg_decompress_lz4.argtypes = [vp, i64, vp, i64, i64, i64, vp, vp]
+        L.bsg_decompress_lz4.restype = i32
+        L.bsg_read_header.argtypes = [vp, i64, ctypes.POINTER(Header)]
+        L.bsg_read_header.restype = i32
+        _LIB = L
+    return _LIB
+
+
+def lib():
+    return _lib()
+
+
+def check(code: int, what: str) -> None:
+    if code != BSG_OK:
+        raise BsgError(code, what)

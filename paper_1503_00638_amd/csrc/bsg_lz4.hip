@@ -1,0 +1,693 @@
+// Stage 2b: per-block LZ4 after the bit transpose (Section 4.2 of Masui et
+// al.: each block is transposed and compressed while it is still on chip;
+// blocks are independent).  On gfx950 a block lives in LDS and one
+// wavefront owns it.
+//
+// Compression = k_encode (transpose into LDS [+ fused rounding], LDS hash
+// table, greedy parse, write to a bound-sized slot) -> k_tile_sum ->
+// k_tile_offsets (one workgroup) -> k_write_offsets -> k_pack (copy slots to
+// their final place, header, raw tail).
+// Decompression = k_decode (stage the LZ4 block in LDS, decode into LDS,
+// inverse transpose on the way out to HBM).
+#include "bsg_internal.hpp"
+#include "bsg_round_dev.hpp"
+#include "bsg_shuffle_dev.hpp"
+
+namespace bsg {
+
+namespace {
+
+constexpr int kSmallBlock = 8192;     // LDS-resident block for the hot path
+constexpr int kLargeBlock = 65536;
+constexpr int kTile = 1024;           // blocks per scan tile
+
+struct EncArgs {
+    const uint8_t *in; // first element of the buffer
+    int64_t nb, E, n_full, last;
+    uint8_t *slots;
+    int64_t slot_bytes;
+    int32_t *sizes;
+    int64_t block0; // index of the first block of this launch
+};
+
+__device__ __forceinline__ uint32_t lds_le32(const uint32_t *b32, int pos)
+{
+    const uint32_t w0 = b32[pos >> 2], w1 = b32[(pos >> 2) + 1];
+    return __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)(pos & 3));
+}
+
+// ---- stage the block into LDS as bit planes -------------------------------
+template <int E, bool ROUND>
+__device__ __forceinline__ void stage_fast(const uint8_t *__restrict__ src, int64_t elems,
+                                           uint8_t *lds, const RoundParams &rp,
+                                           int64_t first_elem)
+{
+    const int lane = threadIdx.x;
+    const int64_t units = elems / Unit<E>::G;
+    for (int64_t u = lane; u < units; u += kWave) {
+        uint32_t w[Unit<E>::IN_WORDS];
+        load_unit<E>(src + u * (Unit<E>::G * E), w);
+        if constexpr (ROUND) {
+            // E == 4: the unit is 32 float32 = 16 complex64 visibilities.
+            const int64_t ci0 = (first_elem + u * 32) / 2;
+            int64_t row = ci0 / rp.T;
+            int64_t t = ci0 - row * rp.T;
+            int64_t fr = row / rp.P;
+            int64_t p = row - fr * rp.P;
+            int32_t i, j;
+            product_pair(rp, p, i, j);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const float ai = rp.autos[(fr * rp.I + i) * rp.T + t];
+                const float aj = rp.autos[(fr * rp.I + j) * rp.T + t];
+                const float2 o = round_complex(make_float2(__uint_as_float(w[2 * k]),
+                                                           __uint_as_float(w[2 * k + 1])),
+                                               ai, aj, i == j, rp);
+                w[2 * k] = __float_as_uint(o.x);
+                w[2 * k + 1] = __float_as_uint(o.y);
+                if (++t == rp.T) {
+                    t = 0;
+                    if (++p == rp.P) {
+                        p = 0;
+                        ++fr;
+                    }
+                    product_pair(rp, p, i, j);
+                }
+            }
+        }
+        unit_forward<E>(w);
+        store_planes<E>(lds, elems / 8, u, w);
+    }
+}
+
+// Generic staging with the rounding fused in: element e of the buffer is
+// component e & 1 of visibility e >> 1; each lane rounds its own element and
+// the block is transposed with ballots.
+__device__ __forceinline__ void block_forward_ballot_round(const uint8_t *__restrict__ in,
+                                                           uint8_t *out, int64_t elems,
+                                                           const RoundParams &rp,
+                                                           int64_t first_elem)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t pb = elems / 8;
+    for (int64_t g = 0; g < elems; g += 64) {
+        const int64_t i = g + lane;
+        uint32_t v = 0;
+        if (i < elems) {
+            uint32_t x = 0;
+            for (int k = 0; k < 4; ++k) x |= (uint32_t)in[i * 4 + k] << (8 * k);
+            v = round_element(x, first_elem + i, rp);
+        }
+        const int64_t rem = (elems - g) / 8;
+        const int nbytes = rem < 8 ? (int)rem : 8;
+        for (int bit = 0; bit < 32; ++bit) {
+            const uint64_t m = __ballot((v >> bit) & 1u);
+            if (lane < nbytes) out[bit * pb + g / 8 + lane] = (uint8_t)(m >> (8 * lane));
+        }
+    }
+}
+
+// EC: the element size this kernel instance has a register fast path for
+// (1, 2, 4, 8, 12, 16), or 0 for the generic ballot path only.
+template <int EC, bool ROUND>
+__device__ __forceinline__ void stage_block(const uint8_t *__restrict__ src, int64_t elems,
+                                            int64_t E, uint8_t *lds, const RoundParams &rp,
+                                            int64_t first_elem)
+{
+    if constexpr (ROUND) {
+        static_assert(EC == 4 || EC == 0, "rounding is fused for float32 elements only");
+        if (EC == 4 && elems % 32 == 0 && ((uintptr_t)src % 16) == 0)
+            stage_fast<4, true>(src, elems, lds, rp, first_elem);
+        else
+            block_forward_ballot_round(src, lds, elems, rp, first_elem);
+    } else {
+        if constexpr (EC != 0) {
+            if (elems % Unit<EC>::G == 0 && ((uintptr_t)src % 16) == 0) {
+                stage_fast<EC, false>(src, elems, lds, rp, first_elem);
+                return;
+            }
+        }
+        block_forward_ballot(src, lds, elems, E);
+    }
+}
+
+// ---- LZ4 emission (wave-cooperative, uniform control flow) ------------------
+__device__ __forceinline__ void put_len_ext(uint8_t *dst, int op, int r, int next)
+{
+    // r = length - 15 >= 0 encoded as next bytes: 255 ... 255, r % 255
+    for (int i = threadIdx.x; i < next; i += kWave)
+        dst[op + i] = (i < next - 1) ? (uint8_t)255 : (uint8_t)(r % 255);
+}
+
+__device__ __forceinline__ int emit(uint8_t *__restrict__ dst, int op, const uint8_t *lits,
+                                    int ll, int offset, int ml, bool last)
+{
+    const int lane = threadIdx.x;
+    const int mlc = last ? 0 : ml - kMinMatch;
+    const int lext = ll >= 15 ? (ll - 15) / 255 + 1 : 0;
+    if (lane == 0) dst[op] = (uint8_t)(((ll < 15 ? ll : 15) << 4) | (mlc < 15 ? mlc : 15));
+    put_len_ext(dst, op + 1, ll - 15, lext);
+    op += 1 + lext;
+    for (int i = lane; i < ll; i += kWave) dst[op + i] = lits[i];
+    op += ll;
+    if (!last) {
+        if (lane == 0) {
+            dst[op] = (uint8_t)(offset & 255);
+            dst[op + 1] = (uint8_t)(offset >> 8);
+        }
+        op += 2;
+        const int mext = mlc >= 15 ? (mlc - 15) / 255 + 1 : 0;
+        put_len_ext(dst, op, mlc - 15, mext);
+        op += mext;
+    }
+    return op;
+}
+
+// ---- the fixed-rule LZ4 encoder of one LDS-resident block -----------------
+// b32: block bytes (n <= MAXB) followed by >= 8 readable padding bytes.
+template <int MAXB>
+__device__ int encode_block(const uint32_t *b32, int n, uint32_t *table, uint16_t *gcand,
+                            uint64_t *gmask, uint8_t *__restrict__ dst)
+{
+    const int lane = threadIdx.x;
+    const uint8_t *b8 = reinterpret_cast<const uint8_t *>(b32);
+    for (int i = lane; i < (1 << kHashBits) / 4; i += kWave)
+        reinterpret_cast<uint4 *>(table)[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+
+    const int last_q = n - kMfLimit;      // last position a match may start at
+    const int last_ins = n - kMinMatch;   // last position with a defined hash
+    int anchor = 0, pnext = 0, op = 0;
+    for (int g0 = 0; g0 <= last_q; g0 += kGroup) {
+        // Candidates for the 8 chunks of this group.  Table entries hold
+        // position + 1 (0 = empty).  Per chunk every lane first reads, then
+        // all lanes raise the entry to their own position: the in-order LDS
+        // queue of the wave makes chunk c see exactly chunks < c.
+#pragma unroll
+        for (int cc = 0; cc < kGroup / kChunk; ++cc) {
+            const int c0 = g0 + cc * kChunk;
+            uint64_t m = 0;
+            if (c0 <= last_q) {
+                const int p = c0 + lane;
+                const bool ins = p <= last_ins, qry = p <= last_q;
+                const uint32_t v = lds_le32(b32, p < MAXB ? p : MAXB);
+                const uint32_t h = (v * kHashMult) >> (32 - kHashBits);
+                uint32_t cand = 0;
+                if (qry) cand = table[h];
+                if (ins) atomicMax(&table[h], (uint32_t)(p + 1));
+                bool ok = false;
+                if (qry && cand != 0) ok = lds_le32(b32, (int)cand - 1) == v;
+                m = __ballot(ok);
+                gcand[cc * kChunk + lane] = (uint16_t)(cand - 1);
+            }
+            if (lane == 0) gmask[cc] = m;
+        }
+        __syncthreads();
+
+        // Greedy parse of the matches that start inside this group.
+        const int gend = min(g0 + kGroup, last_q + 1);
+        for (;;) {
+            const int start = max(pnext, g0);
+            if (start >= gend) break;
+            int q = -1;
+            for (int w = (start - g0) >> 6; w < kGroup / kChunk; ++w) {
+                uint64_t mm = gmask[w];
+                if (w == ((start - g0) >> 6)) mm &= ~0ull << ((start - g0) & 63);
+                if (mm) {
+                    q = g0 + w * kChunk + __builtin_ctzll(mm);
+                    break;
+                }
+            }
+            q = __builtin_amdgcn_readfirstlane(q);
+            if (q < 0 || q >= gend) break;
+            const int c = __builtin_amdgcn_readfirstlane((int)gcand[q - g0]);
+            // Forward extension, 256 bytes per step; bytes at or beyond
+            // maxL (the last 5 block bytes) count as mismatches.
+            const int maxL = n - kLastLiterals - q;
+            int L = kMinMatch;
+            while (L < maxL) {
+                const int o = L + 4 * lane;
+                const int pa = c + o < MAXB ? c + o : MAXB;
+                const int pb = q + o < MAXB ? q + o : MAXB;
+                uint32_t diff = lds_le32(b32, pa) ^ lds_le32(b32, pb);
+                const int vb = maxL - o;
+                if (vb < 4) diff |= vb <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (8 * vb));
+                const uint64_t mm = __ballot(diff != 0);
+                if (mm == 0) {
+                    L += 4 * kWave;
+                    continue;
+                }
+                const int fl = __builtin_ctzll(mm);
+                const uint32_t dd = (uint32_t)__shfl((int)diff, fl);
+                L += 4 * fl + (__builtin_ctz(dd) >> 3);
+                break;
+            }
+            L = __builtin_amdgcn_readfirstlane(L);
+            op = emit(dst, op, b8 + anchor, q - anchor, q - c, L, false);
+            pnext = q + L;
+            anchor = pnext;
+        }
+        __syncthreads();
+    }
+    op = emit(dst, op, b8 + anchor, n - anchor, 0, 0, true);
+    return op;
+}
+
+template <int MAXB, int EC, bool ROUND>
+__global__ __launch_bounds__(64) void k_encode(EncArgs a, RoundParams rp)
+{
+    __shared__ uint32_t blk32[MAXB / 4 + 4];
+    __shared__ uint32_t table[1 << kHashBits];
+    __shared__ uint16_t gcand[kGroup];
+    __shared__ uint64_t gmask[kGroup / kChunk];
+    const int64_t b = a.block0 + blockIdx.x;
+    const int64_t elems = b < a.n_full ? a.nb : a.last;
+    const int n = (int)(elems * a.E);
+    const int64_t first = b * a.nb;
+    stage_block<EC, ROUND>(a.in + first * a.E, elems, a.E, reinterpret_cast<uint8_t *>(blk32), rp,
+                           first);
+    if (threadIdx.x < 4) blk32[MAXB / 4 + threadIdx.x] = 0;
+    __syncthreads();
+    const int sz = encode_block<MAXB>(blk32, n, table, gcand, gmask, a.slots + b * a.slot_bytes);
+    if (threadIdx.x == 0) a.sizes[b] = sz;
+}
+
+// ---- sizes -> offsets -------------------------------------------------------
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *sh)
+{
+    // 256-thread inclusive scan helper storage: sh[256]
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int64_t x = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    return sh[t]; // inclusive
+}
+
+// tile_sum[k] = sum of sizes over blocks [k * kTile, (k + 1) * kTile)
+__global__ __launch_bounds__(256) void k_tile_sum(const int32_t *__restrict__ sizes,
+                                                  int64_t n_blocks, int64_t *__restrict__ tile_sum)
+{
+    __shared__ int64_t sh[256];
+    const int64_t base = int64_t(blockIdx.x) * kTile;
+    int64_t s = 0;
+    for (int k = threadIdx.x; k < kTile; k += 256)
+        if (base + k < n_blocks) s += sizes[base + k];
+    const int64_t inc = block_sum_i64(s, sh);
+    if (threadIdx.x == 255) tile_sum[blockIdx.x] = inc;
+}
+
+// One workgroup: exclusive scan of the tile sums (in place), stream total,
+// capacity verdict, stream header.
+__global__ __launch_bounds__(256) void k_tile_offsets(int64_t *__restrict__ tile_sum,
+                                                      int64_t n_tiles, int64_t fixed_bytes,
+                                                      int64_t cap, int64_t *__restrict__ d_nbytes,
+                                                      uint8_t *__restrict__ out, bsg_header hdr)
+{
+    __shared__ int64_t sh[256];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < n_tiles; base += 256) {
+        const int64_t k = base + threadIdx.x;
+        const int64_t v = k < n_tiles ? tile_sum[k] : 0;
+        const int64_t inc = block_sum_i64(v, sh);
+        if (k < n_tiles) tile_sum[k] = carry + inc - v;
+        carry += sh[255];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t total = fixed_bytes + carry;
+        *d_nbytes = total <= cap ? total : (int64_t)BSG_ECAPACITY;
+        *reinterpret_cast<bsg_header *>(out) = hdr;
+        // payload length at the end of the offset table
+        reinterpret_cast<uint64_t *>(out + kHeaderBytes)[hdr.n_blocks] = (uint64_t)carry;
+    }
+}
+
+// off[b] for every block of a tile (written straight into the stream).
+__global__ __launch_bounds__(256) void k_write_offsets(const int32_t *__restrict__ sizes,
+                                                       int64_t n_blocks,
+                                                       const int64_t *__restrict__ tile_off,
+                                                       uint8_t *__restrict__ out)
+{
+    __shared__ int64_t sh[256];
+    constexpr int PER = kTile / 256;
+    const int64_t base = int64_t(blockIdx.x) * kTile + threadIdx.x * PER;
+    int64_t v[PER];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = base + k < n_blocks ? sizes[base + k] : 0;
+        s += v[k];
+    }
+    const int64_t inc = block_sum_i64(s, sh);
+    int64_t o = tile_off[blockIdx.x] + inc - s;
+    uint64_t *off = reinterpret_cast<uint64_t *>(out + kHeaderBytes);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (base + k < n_blocks) off[base + k] = (uint64_t)o;
+        o += v[k];
+    }
+}
+
+// Copy each block's LZ4 bytes from its slot to the payload; the extra last
+// workgroup copies the raw tail.  Nothing is written when the stream does
+// not fit (d_nbytes < 0).
+__global__ __launch_bounds__(64) void k_pack(const uint8_t *__restrict__ slots, int64_t slot_bytes,
+                                             const int32_t *__restrict__ sizes, int64_t n_blocks,
+                                             uint8_t *__restrict__ out,
+                                             const int64_t *__restrict__ d_nbytes,
+                                             const uint8_t *__restrict__ tail_src,
+                                             int64_t tail_bytes, RoundParams rp, int round_tail,
+                                             int64_t tail_first_elem)
+{
+    if (*d_nbytes < 0) return;
+    const int64_t b = blockIdx.x;
+    const uint64_t *off = reinterpret_cast<const uint64_t *>(out + kHeaderBytes);
+    uint8_t *payload = out + kHeaderBytes + 8 * (n_blocks + 1);
+    const int lane = threadIdx.x;
+    if (b == n_blocks) {
+        uint8_t *dst = payload + off[n_blocks];
+        if (round_tail) { // the raw tail of the fused path is rounded too (float32 elements)
+            for (int64_t k = lane; k < tail_bytes / 4; k += kWave) {
+                uint32_t x = 0;
+                for (int q = 0; q < 4; ++q) x |= (uint32_t)tail_src[4 * k + q] << (8 * q);
+                x = round_element(x, tail_first_elem + k, rp);
+                for (int q = 0; q < 4; ++q) dst[4 * k + q] = (uint8_t)(x >> (8 * q));
+            }
+            return;
+        }
+        for (int64_t i = lane; i < tail_bytes; i += kWave) dst[i] = tail_src[i];
+        return;
+    }
+    const int sz = sizes[b];
+    const uint8_t *src = slots + b * slot_bytes;
+    uint8_t *dst = payload + off[b];
+    // head bytes until dst is 4-byte aligned, then aligned dword stores
+    // assembled from two source dwords, then tail bytes
+    const int head = (int)((4 - ((uintptr_t)dst & 3)) & 3) < sz ? (int)((4 - ((uintptr_t)dst & 3)) & 3) : sz;
+    if (lane < head) dst[lane] = src[lane];
+    const int body = (sz - head) / 4;
+    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src); // slot is 16-byte aligned
+    uint32_t *d32 = reinterpret_cast<uint32_t *>(dst + head);
+    const int sh = head; // source byte offset of the body start
+    for (int w = lane; w < body; w += kWave) {
+        const int sp = sh + 4 * w;
+        const uint32_t lo = s32[sp >> 2];
+        const uint32_t hi = s32[(sp >> 2) + 1]; // within the slot (slot_bytes >= size + 16)
+        d32[w] = __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)(sp & 3));
+    }
+    for (int i = head + 4 * body + lane; i < sz; i += kWave) dst[i] = src[i];
+}
+
+// ---- decoder --------------------------------------------------------------
+struct DecArgs {
+    const uint8_t *in;
+    int64_t in_nbytes;
+    uint8_t *out;
+    int64_t n, E, nb, n_full, last, n_blocks, tail;
+    int32_t *status;
+    int fast_out; // out is 16-byte aligned
+};
+
+__device__ __forceinline__ void fail(int32_t *status)
+{
+    if (threadIdx.x == 0) atomicCAS(status, 0, BSG_ECORRUPT);
+}
+
+// Read an LZ4 length continuation (255-runs then a byte < 255) at ip, 64
+// bytes per step.  Returns false when the input ends first.
+__device__ __forceinline__ bool read_len_ext(const uint8_t *ci, int &ip, int iend, int &len)
+{
+    const int lane = threadIdx.x;
+    for (;;) {
+        const int pos = ip + lane;
+        const uint32_t v = pos < iend ? ci[pos] : 0u;
+        const uint64_t m = __ballot(v != 255u);
+        if (m == 0) {
+            len += 255 * kWave;
+            ip += kWave;
+            continue;
+        }
+        const int f = __builtin_ctzll(m);
+        if (ip + f >= iend) return false;
+        len += 255 * f + __shfl((int)v, f);
+        ip += f + 1;
+        return true;
+    }
+}
+
+// Decode one LZ4 block ci[ip0, iend) into co[0, ob).  Returns false on any
+// malformed input; every read and write is bounds-checked per sequence.
+__device__ bool decode_block(const uint8_t *ci, int ip0, int iend, uint8_t *co, int ob)
+{
+    const int lane = threadIdx.x;
+    int ip = ip0, op = 0;
+    for (;;) {
+        if (ip >= iend) return false;
+        const uint32_t tok = __builtin_amdgcn_readfirstlane(ci[ip]);
+        ++ip;
+        int ll = (int)(tok >> 4);
+        if (ll == 15 && !read_len_ext(ci, ip, iend, ll)) return false;
+        ll = __builtin_amdgcn_readfirstlane(ll);
+        ip = __builtin_amdgcn_readfirstlane(ip);
+        if (ll > iend - ip || ll > ob - op) return false;
+        for (int i = lane; i < ll; i += kWave) co[op + i] = ci[ip + i];
+        ip += ll;
+        op += ll;
+        if (ip == iend) break;
+        if (iend - ip < 2) return false;
+        const int off = __builtin_amdgcn_readfirstlane((int)ci[ip] | ((int)ci[ip + 1] << 8));
+        ip += 2;
+        if (off == 0 || off > op) return false;
+        int ml = (int)(tok & 15) + kMinMatch;
+        if ((tok & 15) == 15 && !read_len_ext(ci, ip, iend, ml)) return false;
+        ml = __builtin_amdgcn_readfirstlane(ml);
+        ip = __builtin_amdgcn_readfirstlane(ip);
+        if (ml > ob - op) return false;
+        if (off >= kWave) {
+            for (int k = 0; k < ml; k += kWave)
+                if (k + lane < ml) co[op + k + lane] = co[op - off + k + lane];
+        } else {
+            // period-off pattern: out[op + i] = out[op - off + i mod off]
+            const int P = off * (kWave / off);
+            const int src = op - off + lane % off;
+            for (int k = 0; k < ml; k += P)
+                if (lane < P && k + lane < ml) co[op + k + lane] = co[src];
+        }
+        op += ml;
+    }
+    return op == ob;
+}
+
+template <int E>
+__device__ __forceinline__ void unstage_fast(const uint8_t *lds, int64_t elems,
+                                             uint8_t *__restrict__ dst)
+{
+    const int64_t units = elems / Unit<E>::G;
+    for (int64_t u = threadIdx.x; u < units; u += kWave) {
+        uint32_t w[Unit<E>::IN_WORDS];
+        load_planes<E>(lds, elems / 8, u, w);
+        unit_inverse<E>(w);
+        store_unit<E>(dst + u * (Unit<E>::G * E), w);
+    }
+}
+
+template <int EC>
+__device__ __forceinline__ void unstage_block(const uint8_t *lds, int64_t elems, int64_t E,
+                                              uint8_t *__restrict__ dst, bool fast_out)
+{
+    if constexpr (EC != 0) {
+        if (fast_out && elems % Unit<EC>::G == 0) {
+            unstage_fast<EC>(lds, elems, dst);
+            return;
+        }
+    }
+    block_inverse_bits(lds, dst, elems, E);
+}
+
+template <int MAXB, int EC>
+__global__ __launch_bounds__(64) void k_decode(DecArgs a)
+{
+    constexpr int kInBytes = (int)(MAXB + MAXB / 255 + 16) + 8;
+    __shared__ uint32_t cin32[(kInBytes + 3) / 4];
+    __shared__ uint32_t cout32[MAXB / 4];
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t table_end = kHeaderBytes + 8 * (a.n_blocks + 1);
+    const int64_t tail_bytes = a.tail * a.E;
+    const int64_t payload_len = a.in_nbytes - table_end - tail_bytes; // >= 0 (host-checked)
+    const uint8_t *payload = a.in + table_end;
+    if (b == a.n_blocks) {
+        // header check and raw tail
+        const bsg_header *h = reinterpret_cast<const bsg_header *>(a.in);
+        const uint64_t *off = reinterpret_cast<const uint64_t *>(a.in + kHeaderBytes);
+        if (h->magic != BSG_MAGIC || h->elem_size != (uint32_t)a.E || h->n != (uint64_t)a.n ||
+            h->block_elems != (uint32_t)a.nb || h->n_blocks != (uint32_t)a.n_blocks ||
+            off[0] != 0 || off[a.n_blocks] != (uint64_t)payload_len) {
+            fail(a.status);
+            return;
+        }
+        uint8_t *dst = a.out + (a.n - a.tail) * a.E;
+        for (int64_t i = lane; i < tail_bytes; i += kWave) dst[i] = payload[payload_len + i];
+        return;
+    }
+    const int64_t elems = b < a.n_full ? a.nb : a.last;
+    const int ob = (int)(elems * a.E);
+    const uint64_t *off = reinterpret_cast<const uint64_t *>(a.in + kHeaderBytes);
+    const uint64_t o0 = off[b], o1 = off[b + 1];
+    if (o0 > o1 || o1 > (uint64_t)payload_len || o1 - o0 > (uint64_t)lz4_bound(ob)) {
+        fail(a.status);
+        return;
+    }
+    const int len = (int)(o1 - o0);
+    // stage: aligned dwords, the first and last possibly partial
+    const uint8_t *src = payload + o0;
+    const int s = (int)((uintptr_t)src & 3);
+    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src - s);
+    const int words = (s + len + 3) >> 2;
+    const uint8_t *in_end = a.in + a.in_nbytes;
+    for (int w = lane; w < words; w += kWave) {
+        const uint8_t *wp = reinterpret_cast<const uint8_t *>(s32 + w);
+        if (wp + 4 <= in_end) {
+            cin32[w] = s32[w];
+        } else {
+            uint32_t v = 0;
+            for (int k = 0; k < 4; ++k)
+                if (wp + k < in_end) v |= (uint32_t)wp[k] << (8 * k);
+            cin32[w] = v;
+        }
+    }
+    __syncthreads();
+    uint8_t *co = reinterpret_cast<uint8_t *>(cout32);
+    const bool ok = decode_block(reinterpret_cast<const uint8_t *>(cin32), s, s + len, co, ob);
+    __syncthreads();
+    if (!ok) {
+        fail(a.status);
+        return;
+    }
+    unstage_block<EC>(co, elems, a.E, a.out + b * a.nb * a.E, a.fast_out != 0);
+}
+
+template <int MAXB, int EC, bool ROUND>
+hipError_t encode_launch(const EncArgs &ea, int64_t nblocks, const RoundParams &rp,
+                         hipStream_t s)
+{
+    if (nblocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_encode<MAXB, EC, ROUND>), dim3((unsigned)nblocks), dim3(kWave), 0, s, ea,
+                       rp);
+    return hipGetLastError();
+}
+
+template <int MAXB>
+hipError_t encode_dispatch(const EncArgs &ea, int64_t nblocks, const RoundParams *rp, int ec,
+                           hipStream_t s)
+{
+    const RoundParams none{};
+    if (rp) return ec == 4 ? encode_launch<MAXB, 4, true>(ea, nblocks, *rp, s)
+                           : encode_launch<MAXB, 0, true>(ea, nblocks, *rp, s);
+    switch (ec) {
+    case 1: return encode_launch<MAXB, 1, false>(ea, nblocks, none, s);
+    case 2: return encode_launch<MAXB, 2, false>(ea, nblocks, none, s);
+    case 4: return encode_launch<MAXB, 4, false>(ea, nblocks, none, s);
+    case 8: return encode_launch<MAXB, 8, false>(ea, nblocks, none, s);
+    case 12: return encode_launch<MAXB, 12, false>(ea, nblocks, none, s);
+    case 16: return encode_launch<MAXB, 16, false>(ea, nblocks, none, s);
+    default: return encode_launch<MAXB, 0, false>(ea, nblocks, none, s);
+    }
+}
+
+template <int MAXB, int EC>
+hipError_t decode_launch(const DecArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_decode<MAXB, EC>), dim3((unsigned)(a.n_blocks + 1)), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int MAXB>
+hipError_t decode_dispatch(const DecArgs &a, int ec, hipStream_t s)
+{
+    switch (ec) {
+    case 1: return decode_launch<MAXB, 1>(a, s);
+    case 2: return decode_launch<MAXB, 2>(a, s);
+    case 4: return decode_launch<MAXB, 4>(a, s);
+    case 8: return decode_launch<MAXB, 8>(a, s);
+    case 12: return decode_launch<MAXB, 12>(a, s);
+    case 16: return decode_launch<MAXB, 16>(a, s);
+    default: return decode_launch<MAXB, 0>(a, s);
+    }
+}
+
+// The element class with a register fast path, or 0.
+inline int element_class(int64_t E) { return unit_elems(E) ? (int)E : 0; }
+
+} // namespace
+
+int64_t compress_workspace(const Layout &L)
+{
+    const int64_t slot = (lz4_bound(L.block_bytes()) + 15) / 16 * 16;
+    const int64_t n_tiles = (L.n_blocks + kTile - 1) / kTile;
+    int64_t ws = L.n_blocks * slot;
+    ws = (ws + 255) / 256 * 256 + ((L.n_blocks * 4 + 255) / 256) * 256;
+    ws += ((n_tiles * 8 + 255) / 256) * 256;
+    return ws > 0 ? ws : 256;
+}
+
+hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int64_t cap,
+                           int64_t *d_nbytes, void *ws, int64_t ws_bytes, const RoundParams *rp,
+                           hipStream_t s)
+{
+    (void)ws_bytes;
+    const int64_t slot = (lz4_bound(L.block_bytes()) + 15) / 16 * 16;
+    const int64_t n_tiles = (L.n_blocks + kTile - 1) / kTile;
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    uint8_t *slots = w;
+    int64_t pos = (L.n_blocks * slot + 255) / 256 * 256;
+    int32_t *sizes = reinterpret_cast<int32_t *>(w + pos);
+    pos += ((L.n_blocks * 4 + 255) / 256) * 256;
+    int64_t *tile_sum = reinterpret_cast<int64_t *>(w + pos);
+
+    EncArgs ea{in, L.nb, L.E, L.n_full, L.last, slots, slot, sizes, 0};
+    RoundParams none{};
+    const int ec = element_class(L.E);
+    hipError_t e = L.block_bytes() <= kSmallBlock
+                       ? encode_dispatch<kSmallBlock>(ea, L.n_blocks, rp, ec, s)
+                       : encode_dispatch<kLargeBlock>(ea, L.n_blocks, rp, ec, s);
+    if (e != hipSuccess) return e;
+
+    bsg_header hdr{BSG_MAGIC, (uint32_t)L.E, (uint64_t)L.n, (uint32_t)L.nb, (uint32_t)L.n_blocks};
+    const int64_t fixed = kHeaderBytes + 8 * (L.n_blocks + 1) + L.tail * L.E;
+    if (n_tiles > 0) {
+        hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)n_tiles), dim3(256), 0, s, sizes, L.n_blocks,
+                           tile_sum);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(256), 0, s, tile_sum, n_tiles, fixed, cap,
+                       d_nbytes, out, hdr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (n_tiles > 0) {
+        hipLaunchKernelGGL(k_write_offsets, dim3((unsigned)n_tiles), dim3(256), 0, s, sizes,
+                           L.n_blocks, tile_sum, out);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const uint8_t *tail_src = in + (L.n - L.tail) * L.E;
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)(L.n_blocks + 1)), dim3(kWave), 0, s, slots, slot,
+                       sizes, L.n_blocks, out, d_nbytes, tail_src, L.tail * L.E,
+                       rp ? *rp : none, rp ? 1 : 0, L.n - L.tail);
+    return hipGetLastError();
+}
+
+hipError_t launch_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, const Layout &L,
+                             int32_t *d_status, hipStream_t s)
+{
+    DecArgs a{in,     in_nbytes,  out,    L.n,        L.E,    L.nb, L.n_full,
+              L.last, L.n_blocks, L.tail, d_status, ((uintptr_t)out % 16) == 0};
+    const int ec = element_class(L.E);
+    return L.block_bytes() <= kSmallBlock ? decode_dispatch<kSmallBlock>(a, ec, s)
+                                          : decode_dispatch<kLargeBlock>(a, ec, s);
+}
+
+} // namespace bsg

@@ -1,0 +1,70 @@
+"""The C-ABI library: it loads on the CPU and exports every symbol the
+header declares; host-only calls (sizes, header parsing, argument checks
+that need no device) behave as documented.  No device work here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bsg.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(bsg_[a-z0-9_]+)\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1503_00638_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1503_00638_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    syms = declared_symbols()
+    assert "bsg_compress_lz4" in syms and "bsg_round_to_noise" in syms
+    for s in syms:
+        assert hasattr(L, s), s
+    from paper_1503_00638_amd import _lib
+    assert set(_lib.EXPORTS) == set(syms)
+
+
+def test_host_only_calls(L):
+    import oracle
+    for E, B in ((4, 0), (4, 2048), (2, 4096), (1, 8192), (8, 1024), (16, 512), (3, 64)):
+        for n in (0, 1, 7, 8, 12345, 2048 * 5 + 17):
+            assert L.bsg_compress_bound(n, E, B) == oracle.compress_bound(n, E, B)
+            assert L.bsg_block_elems(E, B) == oracle.block_elems(E, B)
+            assert L.bsg_compress_workspace_size(n, E, B) > 0
+    assert L.bsg_block_elems(0, 8) == -1
+    assert L.bsg_block_elems(4, 12) == -1
+    assert L.bsg_compress_bound(100, 4, 65536) == -1  # 256 KiB blocks exceed 16-bit offsets
+    assert L.bsg_strerror(-3) == b"corrupt or mismatched compressed stream"
+
+
+def test_argument_checks_need_no_device(L):
+    vp = ctypes.c_void_p
+    # invalid sizes and parameters are refused before any device call
+    assert L.bsg_bitshuffle(vp(16), vp(32), -1, 4, 0, None) == -1
+    assert L.bsg_bitshuffle(vp(16), vp(32), 64, 4, 12, None) == -1
+    assert L.bsg_bitshuffle(None, None, 64, 4, 0, None) == -1
+    assert L.bsg_round_to_noise(vp(16), vp(16), vp(16), 1, 2, 3, None, 3.9e6, -1.0, None) == -1
+    assert L.bsg_round_to_noise(vp(16), vp(16), vp(16), 1, 2, 3, None, 0.0, 0.01, None) == -1
+    assert L.bsg_decompress_lz4(vp(16), 10, vp(16), 2048, 4, 0, vp(16), None) == -3
+    assert L.bsg_compress_lz4(vp(16), vp(16), 2048, 4, 0, 1 << 20, vp(16), vp(256), 0, None) == -2
+
+
+def test_read_header(L):
+    import numpy as np
+    import oracle
+    import paper_1503_00638_amd as bsg
+    s = oracle.compress(np.arange(5000, dtype=np.int32), 4, 1024)
+    h = bsg.read_header(s.tobytes())
+    assert (h.magic, h.elem_size, h.n, h.block_elems, h.n_blocks) == (0x31475342, 4, 5000, 1024, 5)
+    with pytest.raises(bsg.BsgError):
+        bsg.read_header(b"\0" * 24)

@@ -1,0 +1,272 @@
+"""GPU parity: every HIP output equals the CPU oracle bit for bit.
+
+Inputs are seeded synthetic stand-ins for the paper's workloads (see
+paper_1503_00638_amd/synth.py); the oracle is oracle/ (plain C).  Sizes here
+are small enough for the oracle to finish in seconds while spanning several
+blocks/tiles and ragged tails; the full-size workloads are in
+test_gpu_full.py."""
+import numpy as np
+import pytest
+
+import lz4ref
+import oracle
+from paper_1503_00638_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = 3.9e6
+
+
+@pytest.fixture(scope="module")
+def bsg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1503_00638_amd as m
+    m.load()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def u32(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+# ---------------------------------------------------------------- rounding
+@pytest.mark.parametrize("F,I,T,seed,f", [(16, 8, 64, 0, 0.01), (3, 5, 7, 1, 0.01), (1, 1, 1, 2, 0.1),
+                                          (2, 16, 33, 3, 1e-3), (4, 12, 5, 4, 1e-5), (2, 3, 9, 5, 0.0)])
+def test_round_parity(bsg, F, I, T, seed, f):
+    vis, autos = synth.gen_vis(F, I, T, seed, N)
+    ref = oracle.round_to_noise(vis, autos, N, f)
+    got = host(bsg.round_to_noise(dev(vis), dev(autos), N, f))
+    assert np.array_equal(u32(got), u32(ref))
+
+
+def test_round_special_values(bsg):
+    rng = np.random.default_rng(9)
+    F, I, T = 3, 6, 40
+    vis, autos = synth.gen_vis(F, I, T, 9, N)
+    vf = vis.view(np.float32).reshape(-1)
+    bits = rng.integers(0, 2 ** 32, vf.size // 2, dtype=np.uint64).astype(np.uint32)
+    vf[::2] = bits.view(np.float32)  # every float class: NaN, Inf, subnormal, huge
+    vf[1::7] = np.float32(0.0)
+    vf[3::11] = np.float32(-0.0)
+    autos[0, 0, :5] = [0.0, -1.0, np.nan, np.inf, 1e-40]
+    autos[1, 2, :4] = [3.4e38, 1e-30, 1e30, 1e-45]
+    autos[2] *= np.float32(2.0 ** 60)
+    for f in (0.01, 1e-5, 7.0):
+        ref = oracle.round_to_noise(vis, autos, N, f)
+        got = host(bsg.round_to_noise(dev(vis), dev(autos), N, f))
+        assert np.array_equal(u32(got), u32(ref)), f
+
+
+def test_round_prod_map_and_in_place(bsg):
+    F, I, T = 2, 7, 16
+    vis, autos = synth.gen_vis(F, I, T, 11, N)
+    pairs = synth.product_pairs(I)
+    perm = np.random.default_rng(1).permutation(len(pairs))
+    pm = np.ascontiguousarray(pairs[perm])
+    v2 = np.ascontiguousarray(vis[:, perm])
+    ref = oracle.round_to_noise(v2, autos, N, 0.01, prod_map=pm)
+    d = dev(v2)
+    bsg.round_to_noise(d, dev(autos), N, 0.01, out=d, prod_map=dev(pm))
+    assert np.array_equal(u32(host(d)), u32(ref))
+
+
+# ---------------------------------------------------------------- transpose
+SHUF_CASES = [(4, 2048, 2048 * 9), (4, 2048, 2048 * 3 + 8 * 37 + 5), (1, 8192, 8192 * 2 + 13),
+              (2, 4096, 4096 * 2 + 8 * 3 + 1), (8, 1024, 1024 * 5 + 7), (16, 512, 512 * 4 + 40),
+              (12, 64, 64 * 7 + 24), (3, 2728, 10000), (5, 16, 999), (4, 16, 1000),
+              (1, 8, 64), (2, 64, 63), (4, 65536 // 4, 65536 // 4 * 2 + 100), (4, 0, 5000),
+              (7, 24, 24 * 5), (16, 8, 100), (4, 40, 4000), (1, 136, 136 * 9 + 72)]
+
+
+@pytest.mark.parametrize("E,nb,n", SHUF_CASES)
+def test_bitshuffle_parity(bsg, E, nb, n):
+    rng = np.random.default_rng(E * 7 + n)
+    data = rng.integers(0, 256, n * E, dtype=np.uint8)
+    ref = oracle.bitshuffle(data, E, nb)
+    got = host(bsg.bitshuffle(dev(data), E, nb))
+    assert np.array_equal(got, ref)
+    back = host(bsg.bitunshuffle(dev(ref), E, nb))
+    assert np.array_equal(back, data)
+
+
+def test_bitshuffle_unaligned_pointers(bsg):
+    rng = np.random.default_rng(3)
+    E, nb, n = 4, 2048, 2048 * 3 + 24
+    raw = dev(rng.integers(0, 256, n * E + 8, dtype=np.uint8))
+    x = raw[4:4 + n * E]
+    ref = oracle.bitshuffle(host(x), E, nb)
+    out = torch.empty(n * E + 4, dtype=torch.uint8, device="cuda:0")
+    got = bsg.bitshuffle(x, E, nb, out=out[4:])
+    assert np.array_equal(host(got), ref)
+
+
+@pytest.mark.parametrize("k", [4, 12, 20])
+def test_bitshuffle_gauss_int32(bsg, k):
+    x = synth.gen_gauss_int32(2048 * 16 + 8 * 5, k, k)
+    for E in (1, 2, 4, 8):
+        ref = oracle.bitshuffle(x, E, 8192 // E)
+        got = host(bsg.bitshuffle(dev(x), E, 8192 // E))
+        assert np.array_equal(got, ref), E
+
+
+# ---------------------------------------------------------------- LZ4 streams
+STREAM_CASES = [(4, 2048, 2048 * 6), (4, 2048, 2048 * 6 + 8 * 11 + 3), (2, 4096, 4096 * 3 + 1000),
+                (8, 1024, 1024 * 4 + 9), (1, 8192, 8192 * 3 + 7), (16, 512, 512 * 3 + 16),
+                (3, 64, 999), (4, 16, 1), (4, 16, 0), (4, 8, 64), (12, 512, 2000),
+                (4, 16384, 16384 * 2 + 100), (2, 32768, 32768 + 8)]
+
+
+def stream_inputs(E, n, seed):
+    rng = np.random.default_rng(seed)
+    kinds = [
+        rng.integers(0, 256, n * E, dtype=np.uint8),  # incompressible
+        (rng.integers(0, 4, n * E, dtype=np.uint8) * 17).astype(np.uint8),
+        np.zeros(n * E, np.uint8),
+        np.resize(rng.integers(0, 256, 300, dtype=np.uint8), n * E),
+        synth.gen_walk_int16(n * E // 2 + 1, seed).view(np.uint8)[: n * E].copy(),
+    ]
+    return kinds
+
+
+@pytest.mark.parametrize("E,nb,n", STREAM_CASES)
+def test_compress_parity(bsg, E, nb, n):
+    for data in stream_inputs(E, n, E * 31 + n):
+        ref = oracle.compress(data, E, nb)
+        x = dev(data) if data.size else torch.empty(0, dtype=torch.uint8, device="cuda:0")
+        got = host(bsg.compress_sync(x, E, nb))
+        assert got.size == ref.size and np.array_equal(got, ref)
+        back = host(bsg.decompress_sync(dev(ref), n, E, nb))
+        assert np.array_equal(back[: n * E], data)
+
+
+def test_pipeline_config0(bsg):
+    """Tiny plain pipeline: (16, 36, 64) complex64, f = 0.01, 8 KiB blocks."""
+    vis, autos = synth.gen_vis(16, 8, 64, 0, N)
+    r = oracle.round_to_noise(vis, autos, N, 0.01)
+    ref = oracle.compress(r, 4, 2048)
+    dr = bsg.round_to_noise(dev(vis), dev(autos), N, 0.01)
+    s = bsg.compress_sync(dr.view(torch.uint8).reshape(-1), 4, 2048)
+    assert np.array_equal(host(s), ref)
+    fused, nb = bsg.round_compress(dev(vis), dev(autos), N, 0.01, block_size=2048)
+    m = int(host(nb)[0])
+    assert np.array_equal(host(fused)[:m], ref)
+    d = bsg.decompress_sync(s, r.size * 2, 4, 2048)
+    assert np.array_equal(host(d), r.view(np.uint8).reshape(-1))
+
+
+@pytest.mark.parametrize("F,I,T,B", [(3, 5, 7, 2048), (2, 16, 33, 512), (5, 4, 3, 40), (1, 2, 1, 8),
+                                     (4, 8, 64, 0)])
+def test_fused_round_compress(bsg, F, I, T, B):
+    vis, autos = synth.gen_vis(F, I, T, F * I + T, N)
+    for f in (0.01, 0.0, 1e-4):
+        r = oracle.round_to_noise(vis, autos, N, f)
+        ref = oracle.compress(r, 4, B)
+        out, nb = bsg.round_compress(dev(vis), dev(autos), N, f, block_size=B)
+        m = int(host(nb)[0])
+        assert m == ref.size and np.array_equal(host(out)[:m], ref), f
+
+
+def test_decode_liblz4_payloads(bsg):
+    """Streams whose blocks were encoded by the system liblz4 (greedy and HC):
+    the decoder must accept any valid LZ4 block, not only its own."""
+    if not lz4ref.available():
+        pytest.skip("no liblz4")
+    E, nb = 4, 2048
+    vis, autos = synth.gen_vis(4, 8, 64, 7, N)
+    r = oracle.round_to_noise(vis, autos, N, 0.01)
+    sh = oracle.bitshuffle(r, E, nb)
+    n = r.size * 2
+    full, rem = divmod(n, nb)
+    blocks = [sh[b * nb * E:(b + 1) * nb * E].tobytes() for b in range(full)]
+    blocks.append(bytes(nb * E))
+    blocks.append(bytes(range(256)) * (nb * E // 256))
+    data_sh = b"".join(blocks)
+    nblk = len(blocks)
+    for enc in (lz4ref.compress_default, lz4ref.compress_hc):
+        pays = [enc(b) for b in blocks]
+        off = np.zeros(nblk + 1, dtype=np.uint64)
+        off[1:] = np.cumsum([len(p) for p in pays])
+        hdr = np.array([0x31475342, E], dtype=np.uint32).tobytes() + \
+            np.array([nblk * nb], dtype=np.uint64).tobytes() + \
+            np.array([nb, nblk], dtype=np.uint32).tobytes()
+        stream = np.frombuffer(hdr + off.tobytes() + b"".join(pays), dtype=np.uint8)
+        expect = oracle.bitunshuffle(np.frombuffer(data_sh, np.uint8), E, nb)
+        got = host(bsg.decompress_sync(dev(stream), nblk * nb, E, nb))
+        assert np.array_equal(got, expect)
+
+
+def test_decode_rejects_corruption(bsg):
+    E, nb = 4, 2048
+    x = synth.gen_gauss_int32(2048 * 8 + 5, 6, 2)
+    s = oracle.compress(x, E, nb)
+    rng = np.random.default_rng(4)
+    table_end = 24 + 8 * 9
+    n_err = 0
+    for trial in range(60):
+        c = s.copy()
+        kind = trial % 4
+        if kind == 0:
+            i = int(rng.integers(table_end, c.size))
+            c[i] ^= np.uint8(1 << int(rng.integers(0, 8)))
+            nbytes = c.size
+        elif kind == 1:  # offset table entry
+            i = int(rng.integers(24, table_end))
+            c[i] ^= np.uint8(1 << int(rng.integers(0, 8)))
+            nbytes = c.size
+        elif kind == 2:  # header field
+            i = int(rng.integers(0, 24))
+            c[i] ^= np.uint8(1 << int(rng.integers(0, 8)))
+            nbytes = c.size
+        else:  # stream shorter than it claims
+            nbytes = int(rng.integers(table_end + 28, c.size))
+        out, st = bsg.decompress(dev(c), nbytes, x.size, E, nb)
+        code = int(host(st)[0])
+        try:
+            ref = oracle.decompress(c[:nbytes], x.size, E, nb)
+            ref_ok = True
+        except oracle.OracleError:
+            ref_ok = False
+        assert (code == 0) == ref_ok, (trial, code)
+        if ref_ok:
+            assert np.array_equal(host(out)[: x.size * 4], ref)
+        else:
+            assert code == -3
+            n_err += 1
+    assert n_err > 20
+
+
+def test_capacity_verdict(bsg):
+    x = np.random.default_rng(0).integers(0, 256, 2048 * 4 * 4, dtype=np.uint8)
+    ref = oracle.compress(x, 4, 2048)
+    need = bsg.compress_bound(x.size // 4, 4, 2048)
+    out = torch.empty(ref.size - 1, dtype=torch.uint8, device="cuda:0")
+    _, nb = bsg.compress(dev(x), 4, 2048, out=out)
+    assert int(host(nb)[0]) == -2
+    out = torch.empty(ref.size, dtype=torch.uint8, device="cuda:0")
+    _, nb = bsg.compress(dev(x), 4, 2048, out=out)
+    assert int(host(nb)[0]) == ref.size <= need
+    assert np.array_equal(host(out), ref)
+
+
+def test_repeatable_and_stream_order(bsg):
+    vis, autos = synth.gen_vis(8, 16, 32, 5, N)
+    dv, da = dev(vis), dev(autos)
+    outs = []
+    s = torch.cuda.Stream()
+    for k in range(3):
+        with torch.cuda.stream(s if k == 1 else torch.cuda.current_stream()):
+            o, nb = bsg.round_compress(dv, da, N, 0.01, block_size=2048, stream=s if k == 1 else None)
+            torch.cuda.synchronize()
+            outs.append(host(o)[: int(host(nb)[0])])
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
