@@ -111,10 +111,11 @@ int64_t bsg_compress_workspace_size(int64_t n, int64_t elem_size, int64_t block_
 /* Compress n elements into the stream format above.  Every block is
  * bit-transposed and LZ4-encoded with one fixed, deterministic greedy rule
  * (hash of 4 bytes, 12 bits, Knuth's multiplier 2654435761; candidate = the
- * last earlier position with that hash in an earlier 64-position chunk; a
- * match needs 4 equal bytes, starts at p <= len - 12, is extended forward
- * only and keeps the last 5 bytes literal), so the output bytes are a pure
- * function of the input.
+ * last earlier position with that hash in an earlier 64-position chunk; the
+ * candidate is extended forward only, keeping the last 5 bytes literal, and
+ * taken when it covers at least 8 bytes starting at p <= len - 12), so the
+ * output bytes are a pure function of the input.  The result is a standard
+ * LZ4 block that any LZ4 decoder reads.
  * out: out_capacity bytes.  *d_out_nbytes (device int64) receives the
  *   stream length, or BSG_ECAPACITY when it would exceed out_capacity (then
  *   out holds nothing meaningful).  Pass out_capacity >= bsg_compress_bound

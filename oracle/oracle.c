@@ -25,7 +25,8 @@
 #define HASH_BITS 12
 #define HASH_MULT 2654435761u /* Knuth's multiplicative constant */
 #define CHUNK 64             /* candidate table is updated every 64 positions */
-#define MINMATCH 4
+#define MINMATCH 4       /* LZ4 format: match lengths are coded as length - 4 */
+#define MINTAKE 8        /* the rule only takes matches of at least 8 bytes */
 #define MFLIMIT 12       /* a match may start only at p <= n - 12 */
 #define LASTLITERALS 5   /* the last 5 bytes of a block are literals */
 
@@ -306,16 +307,18 @@ int64_t oracle_lz4_compress_block(const uint8_t *x, int64_t n, uint8_t *dst, int
             table[hash4(le32(x + q))] = (int32_t)q;
     }
 
-    /* Greedy parse: a match at p needs a candidate whose first 4 bytes equal
-     * those at p; it is extended forward only (no backward extension, no
-     * lazy evaluation) while keeping the last 5 bytes as literals. */
+    /* Greedy parse: at p, extend the candidate forward only (no backward
+     * extension, no lazy evaluation) while keeping the last 5 bytes as
+     * literals; the match is taken when it covers at least 8 bytes, else p
+     * moves on by one byte. */
     int64_t op = 0, anchor = 0, p = 0;
     while (p <= last_start) {
         const int64_t c = cand[p];
-        if (c >= 0 && le32(x + c) == le32(x + p)) {
-            int64_t L = MINMATCH;
+        int64_t L = 0;
+        if (c >= 0)
             while (p + L < n - LASTLITERALS && x[c + L] == x[p + L])
                 L++;
+        if (L >= MINTAKE) {
             const int64_t ml4 = L - MINMATCH;
             const int64_t off = p - c;
             if (put_literals(dst, &op, cap, x + anchor, p - anchor, ml4 < 15 ? (int)ml4 : 15) ||

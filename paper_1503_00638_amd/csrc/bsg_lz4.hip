@@ -195,8 +195,12 @@ __device__ int encode_block(const uint32_t *b32, int n, uint32_t *table, uint16_
                 uint32_t cand = 0;
                 if (qry) cand = table[h];
                 if (ins) atomicMax(&table[h], (uint32_t)(p + 1));
+                // taken iff the first 8 bytes agree and the match can reach
+                // 8 bytes before the last 5 literals (p <= len - 13)
                 bool ok = false;
-                if (qry && cand != 0) ok = lds_le32(b32, (int)cand - 1) == v;
+                if (qry && p <= last_q - 1 && cand != 0)
+                    ok = lds_le32(b32, (int)cand - 1) == v &&
+                         lds_le32(b32, (int)cand + 3) == lds_le32(b32, p + 4);
                 m = __ballot(ok);
                 gcand[cc * kChunk + lane] = (uint16_t)(cand - 1);
             }
@@ -224,7 +228,7 @@ __device__ int encode_block(const uint32_t *b32, int n, uint32_t *table, uint16_
             // Forward extension, 256 bytes per step; bytes at or beyond
             // maxL (the last 5 block bytes) count as mismatches.
             const int maxL = n - kLastLiterals - q;
-            int L = kMinMatch;
+            int L = kMinTake;
             while (L < maxL) {
                 const int o = L + 4 * lane;
                 const int pa = c + o < MAXB ? c + o : MAXB;
@@ -440,45 +444,163 @@ __device__ __forceinline__ bool read_len_ext(const uint8_t *ci, int &ip, int ien
     }
 }
 
-// Decode one LZ4 block ci[ip0, iend) into co[0, ob).  Returns false on any
-// malformed input; every read and write is bounds-checked per sequence.
-__device__ bool decode_block(const uint8_t *ci, int ip0, int iend, uint8_t *co, int ob)
+// Write the low n (0..4) bytes of v at LDS byte position pos.  mis = pos & 3
+// is the same for every lane of a copy, so the widest aligned stores are
+// chosen uniformly.
+__device__ __forceinline__ void put4(uint8_t *b8, int pos, uint32_t v, int n, int mis)
 {
-    const int lane = threadIdx.x;
+    if (n == 4) {
+        if (mis == 0) {
+            *reinterpret_cast<uint32_t *>(b8 + pos) = v;
+            return;
+        }
+        if (mis == 2) {
+            *reinterpret_cast<uint16_t *>(b8 + pos) = (uint16_t)v;
+            *reinterpret_cast<uint16_t *>(b8 + pos + 2) = (uint16_t)(v >> 16);
+            return;
+        }
+        b8[pos] = (uint8_t)v;
+        *reinterpret_cast<uint16_t *>(b8 + pos + 1) = (uint16_t)(v >> 8);
+        b8[pos + 3] = (uint8_t)(v >> 24);
+        return;
+    }
+    if (n > 0) b8[pos] = (uint8_t)v;
+    if (n > 1) b8[pos + 1] = (uint8_t)(v >> 8);
+    if (n > 2) b8[pos + 2] = (uint8_t)(v >> 16);
+}
+
+// out[op, op + ll) = in[src, src + ll), 256 bytes per step, 4 per lane.
+// Every step reads before it writes; the caller guarantees op <= src so a
+// step never overwrites input a later step still has to read.
+__device__ __forceinline__ void lds_copy(uint8_t *b8, const uint32_t *b32, int op, int src, int ll)
+{
+    const int pos0 = 4 * (int)threadIdx.x;
+    const int mis = op & 3;
+    for (int k = 0; k < ll; k += 4 * kWave) {
+        const int pos = k + pos0;
+        if (pos < ll) {
+            const uint32_t v = lds_le32(b32, src + pos);
+            put4(b8, op + pos, v, ll - pos < 4 ? ll - pos : 4, mis);
+        }
+    }
+}
+
+// LZ4 match: out[op + i] = out[op - off + (i mod off)] for i < ml.  Every
+// source byte lies in [op - off, op), final before the match starts, so all
+// steps are independent; short periods (1..3) are replicated from registers.
+__device__ __forceinline__ void lds_match(uint8_t *b8, const uint32_t *b32, int op, int off, int ml)
+{
+    const int pos0 = 4 * (int)threadIdx.x;
+    const int mis = op & 3;
+    const int base = op - off;
+    if (off >= ml) { // no overlap
+        for (int k = 0; k < ml; k += 4 * kWave) {
+            const int pos = k + pos0;
+            if (pos < ml) put4(b8, op + pos, lds_le32(b32, base + pos), ml - pos < 4 ? ml - pos : 4, mis);
+        }
+        return;
+    }
+    if (off < 4) {
+        const uint32_t p0 = b8[base], p1 = b8[base + (off > 1 ? 1 : 0)], p2 = b8[base + (off > 2 ? 2 : 0)];
+        for (int k = 0; k < ml; k += 4 * kWave) {
+            const int pos = k + pos0;
+            if (pos >= ml) continue;
+            uint32_t v;
+            if (off == 1) {
+                v = p0 * 0x01010101u;
+            } else if (off == 2) { // pos is even
+                v = (p0 | (p1 << 8)) * 0x00010001u;
+            } else {
+                const int r = pos % 3;
+                const uint32_t a = r == 0 ? p0 : (r == 1 ? p1 : p2);
+                const uint32_t b = r == 0 ? p1 : (r == 1 ? p2 : p0);
+                const uint32_t c = r == 0 ? p2 : (r == 1 ? p0 : p1);
+                v = a | (b << 8) | (c << 16) | (a << 24);
+            }
+            put4(b8, op + pos, v, ml - pos < 4 ? ml - pos : 4, mis);
+        }
+        return;
+    }
+    // 4 <= off < ml: a period of off bytes
+    int r = pos0 % off;             // (k + pos0) mod off, advanced per step
+    const int step = (4 * kWave) % off;
+    for (int k = 0; k < ml; k += 4 * kWave) {
+        const int pos = k + pos0;
+        if (pos < ml) {
+            uint32_t v;
+            if (r + 3 < off) {
+                v = lds_le32(b32, base + r);
+            } else {
+                v = 0;
+                for (int j = 0; j < 4; ++j) {
+                    const int rj = r + j < off ? r + j : r + j - off;
+                    v |= (uint32_t)b8[base + rj] << (8 * j);
+                }
+            }
+            put4(b8, op + pos, v, ml - pos < 4 ? ml - pos : 4, mis);
+        }
+        r += step;
+        if (r >= off) r -= off;
+    }
+}
+
+// Decode the LZ4 block held at buf[ip0, iend) into buf[0, ob) in place (the
+// input sits at the tail of the buffer).  Returns false on malformed input:
+// every length, offset and the input/output boundaries are checked once per
+// sequence, and the output may never reach input not yet read.
+__device__ bool decode_inplace(uint32_t *b32, int ip0, int iend, int ob)
+{
+    uint8_t *b8 = reinterpret_cast<uint8_t *>(b32);
     int ip = ip0, op = 0;
+    uint32_t w = __builtin_amdgcn_readfirstlane(lds_le32(b32, ip));
     for (;;) {
         if (ip >= iend) return false;
-        const uint32_t tok = __builtin_amdgcn_readfirstlane(ci[ip]);
-        ++ip;
+        const uint32_t tok = w & 255u;
         int ll = (int)(tok >> 4);
-        if (ll == 15 && !read_len_ext(ci, ip, iend, ll)) return false;
-        ll = __builtin_amdgcn_readfirstlane(ll);
-        ip = __builtin_amdgcn_readfirstlane(ip);
-        if (ll > iend - ip || ll > ob - op) return false;
-        for (int i = lane; i < ll; i += kWave) co[op + i] = ci[ip + i];
-        ip += ll;
-        op += ll;
-        if (ip == iend) break;
-        if (iend - ip < 2) return false;
-        const int off = __builtin_amdgcn_readfirstlane((int)ci[ip] | ((int)ci[ip + 1] << 8));
-        ip += 2;
-        if (off == 0 || off > op) return false;
-        int ml = (int)(tok & 15) + kMinMatch;
-        if ((tok & 15) == 15 && !read_len_ext(ci, ip, iend, ml)) return false;
-        ml = __builtin_amdgcn_readfirstlane(ml);
-        ip = __builtin_amdgcn_readfirstlane(ip);
-        if (ml > ob - op) return false;
-        if (off >= kWave) {
-            for (int k = 0; k < ml; k += kWave)
-                if (k + lane < ml) co[op + k + lane] = co[op - off + k + lane];
-        } else {
-            // period-off pattern: out[op + i] = out[op - off + i mod off]
-            const int P = off * (kWave / off);
-            const int src = op - off + lane % off;
-            for (int k = 0; k < ml; k += P)
-                if (lane < P && k + lane < ml) co[op + k + lane] = co[src];
+        int lit = ip + 1;
+        if (ll == 15) {
+            const int e = (int)((w >> 8) & 255u);
+            if (ip + 1 >= iend) return false;
+            if (e != 255) {
+                ll += e;
+                lit = ip + 2;
+            } else {
+                int q = ip + 1;
+                if (!read_len_ext(b8, q, iend, ll)) return false;
+                lit = __builtin_amdgcn_readfirstlane(q);
+                ll = __builtin_amdgcn_readfirstlane(ll);
+            }
         }
+        if (ll > iend - lit || ll > ob - op || op > lit) return false;
+        const int ip2 = lit + ll;
+        uint32_t ow = lds_le32(b32, ip2); // offset and first length byte
+        lds_copy(b8, b32, op, lit, ll);
+        op += ll;
+        if (ip2 == iend) break;
+        ow = __builtin_amdgcn_readfirstlane(ow);
+        if (iend - ip2 < 2) return false;
+        const int off = (int)(ow & 0xFFFFu);
+        int ml = (int)(tok & 15u) + kMinMatch;
+        int nip = ip2 + 2;
+        if ((tok & 15u) == 15u) {
+            if (nip >= iend) return false;
+            const int e = (int)((ow >> 16) & 255u);
+            if (e != 255) {
+                ml += e;
+                nip = ip2 + 3;
+            } else {
+                int q = ip2 + 2;
+                if (!read_len_ext(b8, q, iend, ml)) return false;
+                nip = __builtin_amdgcn_readfirstlane(q);
+                ml = __builtin_amdgcn_readfirstlane(ml);
+            }
+        }
+        if (off == 0 || off > op || ml > ob - op || op + ml > nip) return false;
+        w = lds_le32(b32, nip); // next token, read together with the match source
+        lds_match(b8, b32, op, off, ml);
+        w = __builtin_amdgcn_readfirstlane(w);
         op += ml;
+        ip = nip;
     }
     return op == ob;
 }
@@ -509,12 +631,17 @@ __device__ __forceinline__ void unstage_block(const uint8_t *lds, int64_t elems,
     block_inverse_bits(lds, dst, elems, E);
 }
 
+// Bytes of the in-place LDS buffer for blocks up to MAXB bytes: the block
+// plus the slack a valid LZ4 block needs so that output never overtakes
+// unread input (any suffix of a block codes its output with at most
+// out/255 + 2 extra bytes), plus alignment.
+template <int MAXB> constexpr int dec_buf_bytes() { return (MAXB + MAXB / 255 + 64 + 3) & ~3; }
+
 template <int MAXB, int EC>
 __global__ __launch_bounds__(64) void k_decode(DecArgs a)
 {
-    constexpr int kInBytes = (int)(MAXB + MAXB / 255 + 16) + 8;
-    __shared__ uint32_t cin32[(kInBytes + 3) / 4];
-    __shared__ uint32_t cout32[MAXB / 4];
+    constexpr int kBuf = dec_buf_bytes<MAXB>();
+    __shared__ uint32_t buf32[kBuf / 4 + 4]; // + over-read padding
     const int lane = threadIdx.x;
     const int64_t b = blockIdx.x;
     const int64_t table_end = kHeaderBytes + 8 * (a.n_blocks + 1);
@@ -544,32 +671,35 @@ __global__ __launch_bounds__(64) void k_decode(DecArgs a)
         return;
     }
     const int len = (int)(o1 - o0);
-    // stage: aligned dwords, the first and last possibly partial
+    // stage the LZ4 block at the tail of the buffer with the same 4-byte
+    // phase as in HBM: aligned dword copies, the last one possibly partial
     const uint8_t *src = payload + o0;
     const int s = (int)((uintptr_t)src & 3);
+    const int base = ((kBuf - len - s) & ~3) + s;
     const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src - s);
     const int words = (s + len + 3) >> 2;
+    const int w0 = (base - s) >> 2;
     const uint8_t *in_end = a.in + a.in_nbytes;
     for (int w = lane; w < words; w += kWave) {
         const uint8_t *wp = reinterpret_cast<const uint8_t *>(s32 + w);
         if (wp + 4 <= in_end) {
-            cin32[w] = s32[w];
+            buf32[w0 + w] = s32[w];
         } else {
             uint32_t v = 0;
             for (int k = 0; k < 4; ++k)
                 if (wp + k < in_end) v |= (uint32_t)wp[k] << (8 * k);
-            cin32[w] = v;
+            buf32[w0 + w] = v;
         }
     }
     __syncthreads();
-    uint8_t *co = reinterpret_cast<uint8_t *>(cout32);
-    const bool ok = decode_block(reinterpret_cast<const uint8_t *>(cin32), s, s + len, co, ob);
+    const bool ok = decode_inplace(buf32, base, base + len, ob);
     __syncthreads();
     if (!ok) {
         fail(a.status);
         return;
     }
-    unstage_block<EC>(co, elems, a.E, a.out + b * a.nb * a.E, a.fast_out != 0);
+    unstage_block<EC>(reinterpret_cast<const uint8_t *>(buf32), elems, a.E,
+                      a.out + b * a.nb * a.E, a.fast_out != 0);
 }
 
 template <int MAXB, int EC, bool ROUND>

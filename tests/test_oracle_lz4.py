@@ -25,7 +25,8 @@ def h(x, q):
 
 def brute_encode(x: bytes) -> bytes:
     """The fixed rule stated directly: cand(p) = largest q <= n-4 with
-    q // 64 < p // 64 and h(q) == h(p), found by scanning every q."""
+    q // 64 < p // 64 and h(q) == h(p), found by scanning every q; a match
+    is taken when it extends to at least 8 bytes."""
     n = len(x)
 
     def cand(p):
@@ -51,10 +52,11 @@ def brute_encode(x: bytes) -> bytes:
     anchor = p = 0
     while p <= n - 12:
         c = cand(p)
-        if c is not None and x[c:c + 4] == x[p:p + 4]:
-            L = 4
+        L = 0
+        if c is not None:
             while p + L < n - 5 and x[c + L] == x[p + L]:
                 L += 1
+        if L >= 8:
             lits(anchor, p, min(L - 4, 15))
             out.extend(((p - c) & 255, (p - c) >> 8))
             if L - 4 >= 15:
@@ -82,6 +84,10 @@ def structured_blocks(rng):
     yield rng.integers(0, 256, 300, dtype=np.uint8).tobytes()
     yield rng.integers(0, 4, 400, dtype=np.uint8).tobytes()
     yield (b"abcdefgh" * 60)[:450]
+    # matches of exactly 7, 8 and 9 bytes around the acceptance threshold
+    base = bytes(rng.integers(0, 256, 64, dtype=np.uint8))
+    for k in (7, 8, 9):
+        yield base + base[:k] + bytes(rng.integers(0, 256, 40, dtype=np.uint8)) + base[3:3 + k] + bytes(20)
     pat = rng.integers(0, 256, 70, dtype=np.uint8).tobytes()
     yield pat * 5 + rng.integers(0, 256, 30, dtype=np.uint8).tobytes() + pat * 2
     x = synth.gen_gauss_int32(96, 3, 1)
@@ -97,8 +103,12 @@ def test_brute_force_rule(oracle_lib):
 
 def test_all_zero_closed_form(oracle_lib):
     """Positions 0..63 have no candidate (chunk 0); p = 64 matches q = 63 at
-    offset 1 and extends to n - 5; then 5 literals close the block."""
-    for n in (76, 200, 4096, 8192, 65536):
+    offset 1 and extends to n - 5; then 5 literals close the block.  The
+    match is taken only when it covers at least 8 bytes (n >= 77); below
+    that the whole block is one literal run."""
+    got = oracle_lib.lz4_compress_block(np.zeros(76, np.uint8))
+    assert got == bytes([0xF0, 76 - 15]) + bytes(76)
+    for n in (77, 200, 4096, 8192, 65536):
         got = oracle_lib.lz4_compress_block(np.zeros(n, np.uint8))
         L = n - 5 - 64
         exp = bytearray([0xF0 | min(L - 4, 15), 64 - 15]) + bytes(64) + bytes([1, 0])
