@@ -85,6 +85,9 @@ def main(argv=None):
     ap.add_argument("--cpu-freqs", type=int, default=256,
                     help="frequencies of the workload the CPU oracle baseline times")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counter scale)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by "
@@ -223,6 +226,12 @@ def main(argv=None):
                      "algorithmic_bytes_per_launch": int(dom_bytes)},
         "source_digest": source_digest(),
     }
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu:
         print("# timing the CPU oracle baseline", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(vis, autos, w, min(args.cpu_freqs, w["F"]))

@@ -36,6 +36,31 @@ __device__ __forceinline__ uint32_t lds_le32(const uint32_t *b32, int pos)
     return __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)(pos & 3));
 }
 
+// Write the low n (0..4) bytes of v at byte position pos of b8 (LDS or HBM).
+// mis = address & 3 is the same for every lane of a copy, so the widest
+// aligned stores are chosen uniformly.
+__device__ __forceinline__ void put4(uint8_t *b8, int pos, uint32_t v, int n, int mis)
+{
+    if (n == 4) {
+        if (mis == 0) {
+            *reinterpret_cast<uint32_t *>(b8 + pos) = v;
+            return;
+        }
+        if (mis == 2) {
+            *reinterpret_cast<uint16_t *>(b8 + pos) = (uint16_t)v;
+            *reinterpret_cast<uint16_t *>(b8 + pos + 2) = (uint16_t)(v >> 16);
+            return;
+        }
+        b8[pos] = (uint8_t)v;
+        *reinterpret_cast<uint16_t *>(b8 + pos + 1) = (uint16_t)(v >> 8);
+        b8[pos + 3] = (uint8_t)(v >> 24);
+        return;
+    }
+    if (n > 0) b8[pos] = (uint8_t)v;
+    if (n > 1) b8[pos + 1] = (uint8_t)(v >> 8);
+    if (n > 2) b8[pos + 2] = (uint8_t)(v >> 16);
+}
+
 // ---- stage the block into LDS as bit planes -------------------------------
 template <int E, bool ROUND>
 __device__ __forceinline__ void stage_fast(const uint8_t *__restrict__ src, int64_t elems,
@@ -139,7 +164,7 @@ __device__ __forceinline__ void put_len_ext(uint8_t *dst, int op, int r, int nex
         dst[op + i] = (i < next - 1) ? (uint8_t)255 : (uint8_t)(r % 255);
 }
 
-__device__ __forceinline__ int emit(uint8_t *__restrict__ dst, int op, const uint8_t *lits,
+__device__ __forceinline__ int emit(uint8_t *__restrict__ dst, int op, const uint32_t *b32, int lit,
                                     int ll, int offset, int ml, bool last)
 {
     const int lane = threadIdx.x;
@@ -148,7 +173,13 @@ __device__ __forceinline__ int emit(uint8_t *__restrict__ dst, int op, const uin
     if (lane == 0) dst[op] = (uint8_t)(((ll < 15 ? ll : 15) << 4) | (mlc < 15 ? mlc : 15));
     put_len_ext(dst, op + 1, ll - 15, lext);
     op += 1 + lext;
-    for (int i = lane; i < ll; i += kWave) dst[op + i] = lits[i];
+    // literals, 4 bytes per lane per step
+    uint8_t *lp = dst + op;
+    const int mis = (int)((uintptr_t)lp & 3);
+    for (int k = 0; k < ll; k += 4 * kWave) {
+        const int pos = k + 4 * lane;
+        if (pos < ll) put4(lp, pos, lds_le32(b32, lit + pos), ll - pos < 4 ? ll - pos : 4, mis);
+    }
     op += ll;
     if (!last) {
         if (lane == 0) {
@@ -164,96 +195,140 @@ __device__ __forceinline__ int emit(uint8_t *__restrict__ dst, int op, const uin
 }
 
 // ---- the fixed-rule LZ4 encoder of one LDS-resident block -----------------
-// b32: block bytes (n <= MAXB) followed by >= 8 readable padding bytes.
+// Length of the common prefix of b[q + L ...] and b[c + L ...] (c < q),
+// capped at maxL: 256 bytes per step first, then 1 KiB per step.  Bytes at or
+// beyond maxL count as mismatches.
 template <int MAXB>
-__device__ int encode_block(const uint32_t *b32, int n, uint32_t *table, uint16_t *gcand,
-                            uint64_t *gmask, uint8_t *__restrict__ dst)
+__device__ __forceinline__ int extend_match(const uint32_t *b32, int c, int q, int L, int maxL)
 {
     const int lane = threadIdx.x;
-    const uint8_t *b8 = reinterpret_cast<const uint8_t *>(b32);
+    if (L >= maxL) return maxL;
+    {
+        const int o = L + 4 * lane;
+        const int pa = c + o < MAXB ? c + o : MAXB;
+        const int pb = q + o < MAXB ? q + o : MAXB;
+        uint32_t diff = lds_le32(b32, pa) ^ lds_le32(b32, pb);
+        const int vb = maxL - o;
+        if (vb < 4) diff |= vb <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (8 * vb));
+        const uint64_t mm = __ballot(diff != 0);
+        if (mm) {
+            const int fl = __builtin_ctzll(mm);
+            const uint32_t dd = (uint32_t)__shfl((int)diff, fl);
+            return L + 4 * fl + (__builtin_ctz(dd) >> 3);
+        }
+        L += 4 * kWave;
+    }
+    while (L < maxL) {
+        const int o = L + 16 * lane;
+        int first = 16; // first differing byte of this lane's 16, 16 = none
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            const int oj = o + 4 * j;
+            const int pa = c + oj < MAXB ? c + oj : MAXB;
+            const int pb = q + oj < MAXB ? q + oj : MAXB;
+            uint32_t diff = lds_le32(b32, pa) ^ lds_le32(b32, pb);
+            const int vb = maxL - oj;
+            if (vb < 4) diff |= vb <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (8 * vb));
+            if (diff) first = 4 * j + (__builtin_ctz(diff) >> 3);
+        }
+        const uint64_t mm = __ballot(first < 16);
+        if (mm) {
+            const int fl = __builtin_ctzll(mm);
+            return L + 16 * fl + __shfl(first, fl);
+        }
+        L += 16 * kWave;
+    }
+    return maxL;
+}
+
+// b32: block bytes (n <= MAXB) followed by >= 12 readable padding bytes.
+// Per group of 512 positions: (1) read 8 bytes at every position, (2) per
+// 64-position chunk read the table entry of every position, then raise the
+// entries to the chunk's positions (the wave's in-order LDS queue makes chunk
+// c see exactly chunks < c), (3) verify 8 bytes at every candidate, (4) parse
+// greedily with the candidate words in VGPRs and the match masks in SGPRs.
+template <int MAXB>
+__device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t *table,
+                                            uint8_t *__restrict__ dst)
+{
+    constexpr int NC = kGroup / kChunk;
+    const int lane = threadIdx.x;
     for (int i = lane; i < (1 << kHashBits) / 4; i += kWave)
         reinterpret_cast<uint4 *>(table)[i] = make_uint4(0, 0, 0, 0);
     __syncthreads();
 
-    const int last_q = n - kMfLimit;      // last position a match may start at
-    const int last_ins = n - kMinMatch;   // last position with a defined hash
+    const int last_q = n - kMfLimit;           // last position a match may start at
+    const int last_take = last_q - 1;          // ... and still reach 8 bytes
+    const int last_ins = n - kMinMatch;        // last position with a defined hash
     int anchor = 0, pnext = 0, op = 0;
     for (int g0 = 0; g0 <= last_q; g0 += kGroup) {
-        // Candidates for the 8 chunks of this group.  Table entries hold
-        // position + 1 (0 = empty).  Per chunk every lane first reads, then
-        // all lanes raise the entry to their own position: the in-order LDS
-        // queue of the wave makes chunk c see exactly chunks < c.
+        uint32_t v[NC], v2[NC], cand[NC];
+        uint64_t m[NC];
 #pragma unroll
-        for (int cc = 0; cc < kGroup / kChunk; ++cc) {
+        for (int cc = 0; cc < NC; ++cc) {
+            const int p = g0 + cc * kChunk + lane;
+            const int pc = p < MAXB ? p : MAXB;
+            const uint32_t *d = b32 + (pc >> 2);
+            const uint32_t d0 = d[0], d1 = d[1], d2 = d[2];
+            v[cc] = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)(pc & 3));
+            v2[cc] = __builtin_amdgcn_alignbyte(d2, d1, (uint32_t)(pc & 3));
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
             const int c0 = g0 + cc * kChunk;
-            uint64_t m = 0;
+            cand[cc] = 0;
             if (c0 <= last_q) {
                 const int p = c0 + lane;
-                const bool ins = p <= last_ins, qry = p <= last_q;
-                const uint32_t v = lds_le32(b32, p < MAXB ? p : MAXB);
-                const uint32_t h = (v * kHashMult) >> (32 - kHashBits);
-                uint32_t cand = 0;
-                if (qry) cand = table[h];
-                if (ins) atomicMax(&table[h], (uint32_t)(p + 1));
-                // taken iff the first 8 bytes agree and the match can reach
-                // 8 bytes before the last 5 literals (p <= len - 13)
-                bool ok = false;
-                if (qry && p <= last_q - 1 && cand != 0)
-                    ok = lds_le32(b32, (int)cand - 1) == v &&
-                         lds_le32(b32, (int)cand + 3) == lds_le32(b32, p + 4);
-                m = __ballot(ok);
-                gcand[cc * kChunk + lane] = (uint16_t)(cand - 1);
+                const bool ins = p <= last_ins;
+                const uint32_t h = (v[cc] * kHashMult) >> (32 - kHashBits);
+                if (p <= last_q) cand[cc] = table[h];
+                // when every inserted position of the chunk holds the same 4
+                // bytes they share one entry: only the largest position writes
+                const uint32_t v0 = __builtin_amdgcn_readfirstlane(v[cc]);
+                const bool uni = __ballot(ins && v[cc] != v0) == 0;
+                const int last_lane = last_ins - c0 < kChunk - 1 ? last_ins - c0 : kChunk - 1;
+                if (ins && (!uni || lane == last_lane)) atomicMax(&table[h], (uint32_t)(p + 1));
             }
-            if (lane == 0) gmask[cc] = m;
         }
-        __syncthreads();
+        // (branch-free so that the 24 reads of the group issue back to back:
+        // a lane without a candidate reads position 0 and is masked after)
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            const int p = g0 + cc * kChunk + lane;
+            const int c = cand[cc] != 0 ? (int)cand[cc] - 1 : 0;
+            const uint32_t *d = b32 + (c >> 2);
+            const uint32_t e0 = d[0], e1 = d[1], e2 = d[2];
+            const bool ok = (p <= last_take) & (cand[cc] != 0) &
+                            (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) == v[cc]) &
+                            (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) == v2[cc]);
+            m[cc] = __ballot(ok);
+        }
 
         // Greedy parse of the matches that start inside this group.
-        const int gend = min(g0 + kGroup, last_q + 1);
         for (;;) {
             const int start = max(pnext, g0);
-            if (start >= gend) break;
-            int q = -1;
-            for (int w = (start - g0) >> 6; w < kGroup / kChunk; ++w) {
-                uint64_t mm = gmask[w];
-                if (w == ((start - g0) >> 6)) mm &= ~0ull << ((start - g0) & 63);
-                if (mm) {
-                    q = g0 + w * kChunk + __builtin_ctzll(mm);
-                    break;
+            if (start > last_take || start >= g0 + kGroup) break;
+            int q = -1, c = 0;
+#pragma unroll
+            for (int w = 0; w < NC; ++w) {
+                const int wb = g0 + w * kChunk;
+                uint64_t mm = m[w];
+                if (start > wb) mm = start - wb >= kChunk ? 0 : (mm & (~0ull << (start - wb)));
+                if (q < 0 && mm) {
+                    const int bit = __builtin_ctzll(mm);
+                    q = wb + bit;
+                    c = __builtin_amdgcn_readlane((int)cand[w], bit) - 1;
                 }
             }
-            q = __builtin_amdgcn_readfirstlane(q);
-            if (q < 0 || q >= gend) break;
-            const int c = __builtin_amdgcn_readfirstlane((int)gcand[q - g0]);
-            // Forward extension, 256 bytes per step; bytes at or beyond
-            // maxL (the last 5 block bytes) count as mismatches.
-            const int maxL = n - kLastLiterals - q;
-            int L = kMinTake;
-            while (L < maxL) {
-                const int o = L + 4 * lane;
-                const int pa = c + o < MAXB ? c + o : MAXB;
-                const int pb = q + o < MAXB ? q + o : MAXB;
-                uint32_t diff = lds_le32(b32, pa) ^ lds_le32(b32, pb);
-                const int vb = maxL - o;
-                if (vb < 4) diff |= vb <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (8 * vb));
-                const uint64_t mm = __ballot(diff != 0);
-                if (mm == 0) {
-                    L += 4 * kWave;
-                    continue;
-                }
-                const int fl = __builtin_ctzll(mm);
-                const uint32_t dd = (uint32_t)__shfl((int)diff, fl);
-                L += 4 * fl + (__builtin_ctz(dd) >> 3);
-                break;
-            }
-            L = __builtin_amdgcn_readfirstlane(L);
-            op = emit(dst, op, b8 + anchor, q - anchor, q - c, L, false);
+            if (q < 0) break;
+            const int L = __builtin_amdgcn_readfirstlane(
+                extend_match<MAXB>(b32, c, q, kMinTake, n - kLastLiterals - q));
+            op = emit(dst, op, b32, anchor, q - anchor, q - c, L, false);
             pnext = q + L;
             anchor = pnext;
         }
-        __syncthreads();
     }
-    op = emit(dst, op, b8 + anchor, n - anchor, 0, 0, true);
+    op = emit(dst, op, b32, anchor, n - anchor, 0, 0, true);
     return op;
 }
 
@@ -262,8 +337,6 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs a, RoundParams rp)
 {
     __shared__ uint32_t blk32[MAXB / 4 + 4];
     __shared__ uint32_t table[1 << kHashBits];
-    __shared__ uint16_t gcand[kGroup];
-    __shared__ uint64_t gmask[kGroup / kChunk];
     const int64_t b = a.block0 + blockIdx.x;
     const int64_t elems = b < a.n_full ? a.nb : a.last;
     const int n = (int)(elems * a.E);
@@ -272,7 +345,7 @@ __global__ __launch_bounds__(64) void k_encode(EncArgs a, RoundParams rp)
                            first);
     if (threadIdx.x < 4) blk32[MAXB / 4 + threadIdx.x] = 0;
     __syncthreads();
-    const int sz = encode_block<MAXB>(blk32, n, table, gcand, gmask, a.slots + b * a.slot_bytes);
+    const int sz = encode_block<MAXB>(blk32, n, table, a.slots + b * a.slot_bytes);
     if (threadIdx.x == 0) a.sizes[b] = sz;
 }
 
@@ -444,31 +517,6 @@ __device__ __forceinline__ bool read_len_ext(const uint8_t *ci, int &ip, int ien
     }
 }
 
-// Write the low n (0..4) bytes of v at LDS byte position pos.  mis = pos & 3
-// is the same for every lane of a copy, so the widest aligned stores are
-// chosen uniformly.
-__device__ __forceinline__ void put4(uint8_t *b8, int pos, uint32_t v, int n, int mis)
-{
-    if (n == 4) {
-        if (mis == 0) {
-            *reinterpret_cast<uint32_t *>(b8 + pos) = v;
-            return;
-        }
-        if (mis == 2) {
-            *reinterpret_cast<uint16_t *>(b8 + pos) = (uint16_t)v;
-            *reinterpret_cast<uint16_t *>(b8 + pos + 2) = (uint16_t)(v >> 16);
-            return;
-        }
-        b8[pos] = (uint8_t)v;
-        *reinterpret_cast<uint16_t *>(b8 + pos + 1) = (uint16_t)(v >> 8);
-        b8[pos + 3] = (uint8_t)(v >> 24);
-        return;
-    }
-    if (n > 0) b8[pos] = (uint8_t)v;
-    if (n > 1) b8[pos + 1] = (uint8_t)(v >> 8);
-    if (n > 2) b8[pos + 2] = (uint8_t)(v >> 16);
-}
-
 // out[op, op + ll) = in[src, src + ll), 256 bytes per step, 4 per lane.
 // Every step reads before it writes; the caller guarantees op <= src so a
 // step never overwrites input a later step still has to read.
@@ -548,7 +596,7 @@ __device__ __forceinline__ void lds_match(uint8_t *b8, const uint32_t *b32, int 
 // input sits at the tail of the buffer).  Returns false on malformed input:
 // every length, offset and the input/output boundaries are checked once per
 // sequence, and the output may never reach input not yet read.
-__device__ bool decode_inplace(uint32_t *b32, int ip0, int iend, int ob)
+__device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend, int ob)
 {
     uint8_t *b8 = reinterpret_cast<uint8_t *>(b32);
     int ip = ip0, op = 0;
