@@ -20,30 +20,38 @@ namespace {
 
 constexpr int kComplexPerThread = 4;
 
+// A wavefront rounds 256 consecutive visibilities; lane l takes elements
+// l, l + 64, l + 128, l + 192 of them, so every load and store instruction
+// of the wave touches 512 contiguous bytes.
 __global__ __launch_bounds__(256) void k_round(const float2 *__restrict__ vin,
                                                float2 *__restrict__ vout, RoundParams rp,
                                                int64_t n_complex)
 {
-    const int64_t e0 = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * kComplexPerThread;
-    if (e0 >= n_complex) return;
-    int64_t row = e0 / rp.T;
-    int64_t t = e0 - row * rp.T;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    int64_t e = wave * (kWave * kComplexPerThread) + lane;
+    if (e >= n_complex) return;
+    int64_t row = e / rp.T;
+    int64_t t = e - row * rp.T;
     int64_t fr = row / rp.P;
     int64_t p = row - fr * rp.P;
     int32_t i, j;
     product_pair(rp, p, i, j);
-    const int64_t cnt = n_complex - e0 < kComplexPerThread ? n_complex - e0 : kComplexPerThread;
-    for (int k = 0; k < cnt; ++k) {
-        const int64_t e = e0 + k;
+    for (int k = 0; k < kComplexPerThread && e < n_complex; ++k) {
         const float2 v = vin[e];
         const float ai = rp.autos[(fr * rp.I + i) * rp.T + t];
         const float aj = rp.autos[(fr * rp.I + j) * rp.T + t];
         vout[e] = round_complex(v, ai, aj, i == j, rp);
-        if (++t == rp.T) {
-            t = 0;
-            if (++p == rp.P) {
-                p = 0;
-                ++fr;
+        // advance by one wave width (64 visibilities)
+        e += kWave;
+        t += kWave;
+        if (t >= rp.T) {
+            while (t >= rp.T) {
+                t -= rp.T;
+                if (++p == rp.P) {
+                    p = 0;
+                    ++fr;
+                }
             }
             product_pair(rp, p, i, j);
         }
@@ -56,8 +64,8 @@ hipError_t launch_round(const float *vin, float *vout, const RoundParams &rp, hi
 {
     const int64_t n_complex = rp.F * rp.P * rp.T;
     if (n_complex == 0) return hipSuccess;
-    const int64_t threads = (n_complex + kComplexPerThread - 1) / kComplexPerThread;
-    const int64_t blocks = (threads + 255) / 256;
+    const int64_t waves = (n_complex + kWave * kComplexPerThread - 1) / (kWave * kComplexPerThread);
+    const int64_t blocks = (waves * kWave + 255) / 256;
     hipLaunchKernelGGL(k_round, dim3((unsigned)blocks), dim3(256), 0, s,
                        reinterpret_cast<const float2 *>(vin), reinterpret_cast<float2 *>(vout),
                        rp, n_complex);

@@ -63,7 +63,11 @@ __device__ __forceinline__ uint32_t round_bits(uint32_t x, int k)
     if (d >= 25 || (d == 24 && ex == 0)) return sign; // |x| < g/2
     if (d == 24) // g/2 <= |x| < g: the tie g/2 goes to 0 (even), else to g
         return sign | (((mag & 0x7FFFFFu) == 0) ? 0u : ((uint32_t)(ex + 1) << 23));
-    const uint32_t inc = (1u << (d - 1)) - 1u + ((mag >> d) & 1u);
+    // parity of floor(|x| / g): bit d of the significand (1.m or 0.m); for
+    // a normal x with d == 23 that is the implicit leading 1, not bit 23 of
+    // the stored magnitude (the exponent's lowest bit)
+    const uint32_t odd = (d == 23 && ex != 0) ? 1u : ((mag >> d) & 1u);
+    const uint32_t inc = (1u << (d - 1)) - 1u + odd;
     return sign | ((mag + inc) & ~((1u << d) - 1u));
 }
 

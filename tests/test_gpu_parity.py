@@ -68,6 +68,41 @@ def test_round_special_values(bsg):
         assert np.array_equal(u32(got), u32(ref)), f
 
 
+def ties_at_binade_inputs():
+    """Crafted rounding cases where g equals the power of two at the start of
+    x's binade (x in [g, 2g)), including the exact tie x = 1.5 g, for even and
+    odd biased exponents.  With f = 1 and N = 6 the cross G2 is V_ii V_jj, and
+    V = 1.5 * 2^K gives k = K."""
+    Ks = list(range(-20, 21))
+    T = len(Ks)
+    autos = np.empty((1, 2, T), dtype=np.float32)
+    autos[0, 0] = [1.5 * 2.0 ** K for K in Ks]
+    autos[0, 1] = autos[0, 0]
+    vis = np.zeros((1, 3, T), dtype=np.complex64)
+    mult = [1.5, 1.25, 1.75, 1.5 + 2 ** -20, 1.5 - 2 ** -20, -1.5, 1.0, 2.0 - 2 ** -22]
+    out = []
+    for m in mult:
+        v = vis.copy()
+        for t, K in enumerate(Ks):
+            g = 2.0 ** K
+            v[0, 1, t] = np.complex64(complex(m * g, -m * g * 0.5))
+            v[0, 0, t] = np.complex64(complex(m * g * 1.5, m * g))
+            v[0, 2, t] = np.complex64(complex(-m * g, m * g))
+        out.append(v)
+    return out, autos
+
+
+def test_round_ties_at_binade(bsg):
+    vs, autos = ties_at_binade_inputs()
+    for v in vs:
+        ref = oracle.round_to_noise(v, autos, 6.0, 1.0)
+        got = host(bsg.round_to_noise(dev(v), dev(autos), 6.0, 1.0))
+        assert np.array_equal(u32(got), u32(ref))
+        fused, nb = bsg.round_compress(dev(v), dev(autos), 6.0, 1.0, block_size=8)
+        m = int(host(nb)[0])
+        assert np.array_equal(host(fused)[:m], oracle.compress(ref, 4, 8))
+
+
 def test_round_prod_map_and_in_place(bsg):
     F, I, T = 2, 7, 16
     vis, autos = synth.gen_vis(F, I, T, 11, N)
