@@ -149,6 +149,67 @@ int bsg_round_compress_lz4(const void *vis_in, const float *autos, int64_t F, in
 int bsg_decompress_lz4(const void *in, int64_t in_nbytes, void *out, int64_t n,
                        int64_t elem_size, int64_t block_size, int32_t *d_status, void *stream);
 
+/* ---- Many independent streams in one pass (Section 4.2) ---------------
+ * A batch is a set of chunks, each compressed into (or decompressed from) a
+ * stream of its own, exactly the stream bsg_compress_lz4 makes for that
+ * chunk alone.  Chunks are independent units like the blocks inside them,
+ * so one persistent kernel per element-size class walks every block of
+ * every chunk; the launches neither allocate nor synchronise with the host,
+ * so a hipGraph can capture them.
+ *
+ * For compression: in = n elements of elem_size bytes (device), out = the
+ *   stream buffer (device, 8-byte aligned) of out_capacity bytes; in_nbytes
+ *   is ignored.
+ * For decompression: in = the stream (device, 8-byte aligned) of in_nbytes
+ *   bytes, out = room for n elements (device); out_capacity is ignored.
+ * block_size: elements per block as for bsg_compress_lz4 (0 = default);
+ *   blocks above 65536 bytes are rejected. */
+typedef struct bsg_chunk {
+    const void *in;
+    int64_t in_nbytes;
+    void *out;
+    int64_t out_capacity;
+    int64_t n;
+    int64_t elem_size;
+    int64_t block_size;
+} bsg_chunk;
+
+/* Bytes of the descriptor table for count chunks, or BSG_EINVAL. */
+int64_t bsg_batch_table_bytes(int32_t count);
+
+/* Fill host_table (host memory, host_table_bytes >= bsg_batch_table_bytes)
+ * from chunks[0..count).  The caller copies the same bytes to a 16-byte
+ * aligned device buffer (d_table below) before the batch call and keeps
+ * both alive, unchanged, until the work has run; a table may be reused for
+ * any number of calls on the same buffers.  The chunk pointers are stored,
+ * not dereferenced.  Errors: BSG_EINVAL for a bad size or block size. */
+int bsg_batch_build_table(const bsg_chunk *chunks, int32_t count, void *host_table,
+                          int64_t host_table_bytes);
+
+/* Device workspace bytes bsg_batch_compress needs for this table. */
+int64_t bsg_batch_workspace_size(const void *host_table);
+
+/* Compress every chunk of the table.  d_nbytes: device int64[count],
+ * entry i (the caller's chunk order) receives chunk i's stream length, or
+ * BSG_ECAPACITY when it would exceed that chunk's out_capacity (then its
+ * out holds nothing meaningful; the other chunks are unaffected).
+ * workspace: 256-byte aligned, workspace_bytes >= bsg_batch_workspace_size.
+ * waves_per_cu: resident workgroups per compute unit of the persistent
+ *   kernels (<= 0: 16).
+ * Errors: BSG_EINVAL (NULL pointers, misaligned buffers), BSG_ECAPACITY
+ *   (workspace too small), BSG_EHIP (launch failure). */
+int bsg_batch_compress(const void *host_table, const void *d_table, int64_t *d_nbytes,
+                       void *workspace, int64_t workspace_bytes, int32_t waves_per_cu,
+                       void *stream);
+
+/* Decompress every chunk of the table (streams from bsg_compress_lz4 or
+ * bsg_batch_compress, or any valid LZ4 encoding of their blocks).
+ * d_status: device int32[count], zero on entry; entry i stays 0 on success
+ * and receives BSG_ECORRUPT when chunk i's stream is invalid, with the same
+ * checks and the same memory bounds as bsg_decompress_lz4. */
+int bsg_batch_decompress(const void *host_table, const void *d_table, int32_t *d_status,
+                         int32_t waves_per_cu, void *stream);
+
 /* Parse a stream header from HOST memory (no device work). */
 int bsg_read_header(const void *host_bytes, int64_t nbytes, bsg_header *hdr);
 

@@ -21,7 +21,7 @@ __all__ = [
     "round_to_noise", "bitshuffle", "bitunshuffle", "compress_bound", "workspace_size",
     "compress", "round_compress", "decompress", "block_elems", "read_header", "BsgError",
     "compress_sync", "decompress_sync", "BSG_OK", "BSG_EINVAL", "BSG_ECAPACITY",
-    "BSG_ECORRUPT", "BSG_EHIP", "load",
+    "BSG_ECORRUPT", "BSG_EHIP", "load", "BatchPlan",
 ]
 
 
@@ -202,6 +202,96 @@ def decompress_sync(s: torch.Tensor, n: int, elem_size: int, block_size: int = 0
     if code != 0:
         raise BsgError(code, "decompress_lz4")
     return out[: n * elem_size]
+
+
+class BatchPlan:
+    """Many chunks, each its own stream, compressed or decompressed by one
+    call of the batch C-ABI.  The plan builds the descriptor table (host and
+    device copies) and allocates every buffer once; compress() / decompress()
+    then only enqueue kernels, so they can be captured into a CUDA graph and
+    replayed.  Tensors referenced by the plan are kept alive by it."""
+
+    def __init__(self, rows, device):
+        L = _lib.lib()
+        self.count = len(rows)
+        self._keep = [t for r in rows for t in (r[0], r[2]) if t is not None]
+        arr = (_lib.Chunk * max(self.count, 1))()
+        for k, (src, in_nbytes, dst, cap, n, e, b) in enumerate(rows):
+            arr[k] = _lib.Chunk(src.data_ptr() if src is not None else None, in_nbytes,
+                                dst.data_ptr() if dst is not None else None, cap, n, e, b)
+        tb = int(L.bsg_batch_table_bytes(self.count))
+        self._host = ctypes.create_string_buffer(tb)
+        _lib.check(L.bsg_batch_build_table(arr, self.count, self._host, tb), "batch_build_table")
+        self._dev = torch.frombuffer(bytearray(self._host.raw), dtype=torch.uint8).to(device)
+        self.device = device
+
+    @classmethod
+    def for_compress(cls, inputs, elem_sizes, block_sizes=0, outs=None):
+        """inputs: device tensors (any dtype, contiguous) of whole elements;
+        outs (optional): uint8 buffers, by default of compress_bound bytes."""
+        k = len(inputs)
+        es = elem_sizes if isinstance(elem_sizes, (list, tuple)) else [elem_sizes] * k
+        bs = block_sizes if isinstance(block_sizes, (list, tuple)) else [block_sizes] * k
+        _require_device(*inputs)
+        device = inputs[0].device if k else torch.device("cuda")
+        rows, buf = [], []
+        for x, e, b in zip(inputs, es, bs):
+            if _nbytes(x) % e:
+                raise ValueError("buffer is not a whole number of elements")
+            n = _nbytes(x) // e
+            buf.append(torch.empty(compress_bound(n, e, b), dtype=torch.uint8, device=device)
+                       if outs is None else outs[len(buf)])
+            rows.append((x, 0, buf[-1], _nbytes(buf[-1]), n, e, b))
+        plan = cls(rows, device)
+        plan.outs = buf
+        ws = int(_lib.lib().bsg_batch_workspace_size(plan._host))
+        plan.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+        plan.nbytes = torch.zeros(max(k, 1), dtype=torch.int64, device=device)
+        return plan
+
+    @classmethod
+    def for_decompress(cls, streams, in_nbytes, ns, elem_sizes, block_sizes=0, outs=None):
+        """streams: device uint8 tensors holding the streams; in_nbytes their
+        lengths; ns the element counts; outs (optional) the destinations."""
+        k = len(streams)
+        es = elem_sizes if isinstance(elem_sizes, (list, tuple)) else [elem_sizes] * k
+        bs = block_sizes if isinstance(block_sizes, (list, tuple)) else [block_sizes] * k
+        _require_device(*streams)
+        device = streams[0].device if k else torch.device("cuda")
+        rows, buf = [], []
+        for s, m, n, e, b in zip(streams, in_nbytes, ns, es, bs):
+            buf.append(torch.empty(max(n * e, 1), dtype=torch.uint8, device=device)
+                       if outs is None else outs[len(buf)])
+            rows.append((s, int(m), buf[-1], 0, int(n), e, b))
+        plan = cls(rows, device)
+        plan.outs = buf
+        plan.status = torch.zeros(max(k, 1), dtype=torch.int32, device=device)
+        return plan
+
+    def compress(self, waves_per_cu: int = 0, stream=None) -> torch.Tensor:
+        """Enqueue; returns the device int64 stream lengths (caller's order)."""
+        _lib.check(_lib.lib().bsg_batch_compress(self._host, _ptr(self._dev), _ptr(self.nbytes),
+                                                  _ptr(self.workspace), _nbytes(self.workspace),
+                                                  waves_per_cu, _stream_ptr(stream)),
+                   "batch_compress")
+        return self.nbytes
+
+    def decompress(self, waves_per_cu: int = 0, stream=None) -> torch.Tensor:
+        """Enqueue; returns the device int32 per-chunk status (0 = ok)."""
+        with torch.cuda.stream(stream) if stream is not None else _nullctx():
+            self.status.zero_()
+        _lib.check(_lib.lib().bsg_batch_decompress(self._host, _ptr(self._dev), _ptr(self.status),
+                                                    waves_per_cu, _stream_ptr(stream)),
+                   "batch_decompress")
+        return self.status
+
+
+class _nullctx:
+    def __enter__(self):
+        return None
+
+    def __exit__(self, *a):
+        return False
 
 
 def read_header(host_bytes: bytes) -> Header:

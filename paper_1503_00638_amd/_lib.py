@@ -22,6 +22,8 @@ EXPORTS = (
     "bsg_strerror", "bsg_block_elems", "bsg_round_to_noise", "bsg_bitshuffle",
     "bsg_bitunshuffle", "bsg_compress_bound", "bsg_compress_workspace_size",
     "bsg_compress_lz4", "bsg_round_compress_lz4", "bsg_decompress_lz4", "bsg_read_header",
+    "bsg_batch_table_bytes", "bsg_batch_build_table", "bsg_batch_workspace_size",
+    "bsg_batch_compress", "bsg_batch_decompress",
 )
 
 
@@ -29,6 +31,13 @@ class Header(ctypes.Structure):
     _fields_ = [("magic", ctypes.c_uint32), ("elem_size", ctypes.c_uint32),
                 ("n", ctypes.c_uint64), ("block_elems", ctypes.c_uint32),
                 ("n_blocks", ctypes.c_uint32)]
+
+
+class Chunk(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p), ("in_nbytes", ctypes.c_int64),
+                ("out", ctypes.c_void_p), ("out_capacity", ctypes.c_int64),
+                ("n", ctypes.c_int64), ("elem_size", ctypes.c_int64),
+                ("block_size", ctypes.c_int64)]
 
 
 class BsgError(RuntimeError):
@@ -72,6 +81,16 @@ def _lib():
         L.bsg_decompress_lz4.restype = i32
         L.bsg_read_header.argtypes = [vp, i64, ctypes.POINTER(Header)]
         L.bsg_read_header.restype = i32
+        L.bsg_batch_table_bytes.argtypes = [ctypes.c_int32]
+        L.bsg_batch_table_bytes.restype = i64
+        L.bsg_batch_build_table.argtypes = [ctypes.POINTER(Chunk), ctypes.c_int32, vp, i64]
+        L.bsg_batch_build_table.restype = i32
+        L.bsg_batch_workspace_size.argtypes = [vp]
+        L.bsg_batch_workspace_size.restype = i64
+        L.bsg_batch_compress.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, vp]
+        L.bsg_batch_compress.restype = i32
+        L.bsg_batch_decompress.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+        L.bsg_batch_decompress.restype = i32
         _LIB = L
     return _LIB
 

@@ -1,0 +1,640 @@
+// Device code of the per-block LZ4 stage (Section 4.2 of Masui et al.:
+// each block is bit-transposed and LZ4-compressed on its own, blocks are
+// independent), shared by the single-stream and the batched kernels.  On
+// gfx950 a block lives in LDS and one wavefront owns it.
+#pragma once
+
+#include "bsg_internal.hpp"
+#include "bsg_round_dev.hpp"
+#include "bsg_shuffle_dev.hpp"
+
+namespace bsg {
+namespace {
+
+
+constexpr int kSmallBlock = 8192;     // LDS-resident block for the hot path
+constexpr int kLargeBlock = 65536;
+constexpr int kTile = 1024;           // blocks per scan tile
+
+__device__ __forceinline__ uint32_t lds_le32(const uint32_t *b32, int pos)
+{
+    const uint32_t w0 = b32[pos >> 2], w1 = b32[(pos >> 2) + 1];
+    return __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)(pos & 3));
+}
+
+// Write the low n (0..4) bytes of v at byte position pos of b8 (LDS or HBM).
+// mis = address & 3 is the same for every lane of a copy, so the widest
+// aligned stores are chosen uniformly.
+__device__ __forceinline__ void put4(uint8_t *b8, int pos, uint32_t v, int n, int mis)
+{
+    if (n == 4) {
+        if (mis == 0) {
+            *reinterpret_cast<uint32_t *>(b8 + pos) = v;
+            return;
+        }
+        if (mis == 2) {
+            *reinterpret_cast<uint16_t *>(b8 + pos) = (uint16_t)v;
+            *reinterpret_cast<uint16_t *>(b8 + pos + 2) = (uint16_t)(v >> 16);
+            return;
+        }
+        b8[pos] = (uint8_t)v;
+        *reinterpret_cast<uint16_t *>(b8 + pos + 1) = (uint16_t)(v >> 8);
+        b8[pos + 3] = (uint8_t)(v >> 24);
+        return;
+    }
+    if (n > 0) b8[pos] = (uint8_t)v;
+    if (n > 1) b8[pos + 1] = (uint8_t)(v >> 8);
+    if (n > 2) b8[pos + 2] = (uint8_t)(v >> 16);
+}
+
+// ---- stage the block into LDS as bit planes -------------------------------
+template <int E, bool ROUND>
+__device__ __forceinline__ void stage_fast(const uint8_t *__restrict__ src, int64_t elems,
+                                           uint8_t *lds, const RoundParams &rp,
+                                           int64_t first_elem)
+{
+    const int lane = threadIdx.x;
+    const int64_t units = elems / Unit<E>::G;
+    for (int64_t u = lane; u < units; u += kWave) {
+        uint32_t w[Unit<E>::IN_WORDS];
+        load_unit<E>(src + u * (Unit<E>::G * E), w);
+        if constexpr (ROUND) {
+            // E == 4: the unit is 32 float32 = 16 complex64 visibilities.
+            const int64_t ci0 = (first_elem + u * 32) / 2;
+            int64_t row = ci0 / rp.T;
+            int64_t t = ci0 - row * rp.T;
+            int64_t fr = row / rp.P;
+            int64_t p = row - fr * rp.P;
+            int32_t i, j;
+            product_pair(rp, p, i, j);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const float ai = rp.autos[(fr * rp.I + i) * rp.T + t];
+                const float aj = rp.autos[(fr * rp.I + j) * rp.T + t];
+                const float2 o = round_complex(make_float2(__uint_as_float(w[2 * k]),
+                                                           __uint_as_float(w[2 * k + 1])),
+                                               ai, aj, i == j, rp);
+                w[2 * k] = __float_as_uint(o.x);
+                w[2 * k + 1] = __float_as_uint(o.y);
+                if (++t == rp.T) {
+                    t = 0;
+                    if (++p == rp.P) {
+                        p = 0;
+                        ++fr;
+                    }
+                    product_pair(rp, p, i, j);
+                }
+            }
+        }
+        unit_forward<E>(w);
+        store_planes<E>(lds, elems / 8, u, w);
+    }
+}
+
+// Generic staging with the rounding fused in: element e of the buffer is
+// component e & 1 of visibility e >> 1; each lane rounds its own element and
+// the block is transposed with ballots.
+__device__ __forceinline__ void block_forward_ballot_round(const uint8_t *__restrict__ in,
+                                                           uint8_t *out, int64_t elems,
+                                                           const RoundParams &rp,
+                                                           int64_t first_elem)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t pb = elems / 8;
+    for (int64_t g = 0; g < elems; g += 64) {
+        const int64_t i = g + lane;
+        uint32_t v = 0;
+        if (i < elems) {
+            uint32_t x = 0;
+            for (int k = 0; k < 4; ++k) x |= (uint32_t)in[i * 4 + k] << (8 * k);
+            v = round_element(x, first_elem + i, rp);
+        }
+        const int64_t rem = (elems - g) / 8;
+        const int nbytes = rem < 8 ? (int)rem : 8;
+        for (int bit = 0; bit < 32; ++bit) {
+            const uint64_t m = __ballot((v >> bit) & 1u);
+            if (lane < nbytes) out[bit * pb + g / 8 + lane] = (uint8_t)(m >> (8 * lane));
+        }
+    }
+}
+
+// EC: the element size this kernel instance has a register fast path for
+// (1, 2, 4, 8, 12, 16), or 0 for the generic ballot path only.
+template <int EC, bool ROUND>
+__device__ __forceinline__ void stage_block(const uint8_t *__restrict__ src, int64_t elems,
+                                            int64_t E, uint8_t *lds, const RoundParams &rp,
+                                            int64_t first_elem)
+{
+    if constexpr (ROUND) {
+        static_assert(EC == 4 || EC == 0, "rounding is fused for float32 elements only");
+        if (EC == 4 && elems % 32 == 0 && ((uintptr_t)src % 16) == 0)
+            stage_fast<4, true>(src, elems, lds, rp, first_elem);
+        else
+            block_forward_ballot_round(src, lds, elems, rp, first_elem);
+    } else {
+        if constexpr (EC != 0) {
+            if (elems % Unit<EC>::G == 0 && ((uintptr_t)src % 16) == 0) {
+                stage_fast<EC, false>(src, elems, lds, rp, first_elem);
+                return;
+            }
+        }
+        block_forward_ballot(src, lds, elems, E);
+    }
+}
+
+// ---- LZ4 emission (wave-cooperative, uniform control flow) ------------------
+__device__ __forceinline__ void put_len_ext(uint8_t *dst, int op, int r, int next)
+{
+    // r = length - 15 >= 0 encoded as next bytes: 255 ... 255, r % 255
+    for (int i = threadIdx.x; i < next; i += kWave)
+        dst[op + i] = (i < next - 1) ? (uint8_t)255 : (uint8_t)(r % 255);
+}
+
+__device__ __forceinline__ int emit(uint8_t *__restrict__ dst, int op, const uint32_t *b32, int lit,
+                                    int ll, int offset, int ml, bool last)
+{
+    const int lane = threadIdx.x;
+    const int mlc = last ? 0 : ml - kMinMatch;
+    const int lext = ll >= 15 ? (ll - 15) / 255 + 1 : 0;
+    if (lane == 0) dst[op] = (uint8_t)(((ll < 15 ? ll : 15) << 4) | (mlc < 15 ? mlc : 15));
+    put_len_ext(dst, op + 1, ll - 15, lext);
+    op += 1 + lext;
+    // literals, 4 bytes per lane per step
+    uint8_t *lp = dst + op;
+    const int mis = (int)((uintptr_t)lp & 3);
+    for (int k = 0; k < ll; k += 4 * kWave) {
+        const int pos = k + 4 * lane;
+        if (pos < ll) put4(lp, pos, lds_le32(b32, lit + pos), ll - pos < 4 ? ll - pos : 4, mis);
+    }
+    op += ll;
+    if (!last) {
+        if (lane == 0) {
+            dst[op] = (uint8_t)(offset & 255);
+            dst[op + 1] = (uint8_t)(offset >> 8);
+        }
+        op += 2;
+        const int mext = mlc >= 15 ? (mlc - 15) / 255 + 1 : 0;
+        put_len_ext(dst, op, mlc - 15, mext);
+        op += mext;
+    }
+    return op;
+}
+
+// ---- the fixed-rule LZ4 encoder of one LDS-resident block -----------------
+// Length of the common prefix of b[q + L ...] and b[c + L ...] (c < q),
+// capped at maxL: 256 bytes per step first, then 1 KiB per step.  Bytes at or
+// beyond maxL count as mismatches.
+template <int MAXB>
+__device__ __forceinline__ int extend_match(const uint32_t *b32, int c, int q, int L, int maxL)
+{
+    const int lane = threadIdx.x;
+    if (L >= maxL) return maxL;
+    {
+        const int o = L + 4 * lane;
+        const int pa = c + o < MAXB ? c + o : MAXB;
+        const int pb = q + o < MAXB ? q + o : MAXB;
+        uint32_t diff = lds_le32(b32, pa) ^ lds_le32(b32, pb);
+        const int vb = maxL - o;
+        if (vb < 4) diff |= vb <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (8 * vb));
+        const uint64_t mm = __ballot(diff != 0);
+        if (mm) {
+            const int fl = __builtin_ctzll(mm);
+            const uint32_t dd = (uint32_t)__shfl((int)diff, fl);
+            return L + 4 * fl + (__builtin_ctz(dd) >> 3);
+        }
+        L += 4 * kWave;
+    }
+    while (L < maxL) {
+        const int o = L + 16 * lane;
+        int first = 16; // first differing byte of this lane's 16, 16 = none
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+            const int oj = o + 4 * j;
+            const int pa = c + oj < MAXB ? c + oj : MAXB;
+            const int pb = q + oj < MAXB ? q + oj : MAXB;
+            uint32_t diff = lds_le32(b32, pa) ^ lds_le32(b32, pb);
+            const int vb = maxL - oj;
+            if (vb < 4) diff |= vb <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (8 * vb));
+            if (diff) first = 4 * j + (__builtin_ctz(diff) >> 3);
+        }
+        const uint64_t mm = __ballot(first < 16);
+        if (mm) {
+            const int fl = __builtin_ctzll(mm);
+            return L + 16 * fl + __shfl(first, fl);
+        }
+        L += 16 * kWave;
+    }
+    return maxL;
+}
+
+// b32: block bytes (n <= MAXB) followed by >= 12 readable padding bytes.
+// Per group of 512 positions: (1) read 8 bytes at every position, (2) per
+// 64-position chunk read the table entry of every position, then raise the
+// entries to the chunk's positions (the wave's in-order LDS queue makes chunk
+// c see exactly chunks < c), (3) verify 8 bytes at every candidate, (4) parse
+// greedily with the candidate words in VGPRs and the match masks in SGPRs.
+template <int MAXB>
+__device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t *table,
+                                            uint8_t *__restrict__ dst)
+{
+    constexpr int NC = kGroup / kChunk;
+    const int lane = threadIdx.x;
+    for (int i = lane; i < (1 << kHashBits) / 4; i += kWave)
+        reinterpret_cast<uint4 *>(table)[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+
+    const int last_q = n - kMfLimit;           // last position a match may start at
+    const int last_take = last_q - 1;          // ... and still reach 8 bytes
+    const int last_ins = n - kMinMatch;        // last position with a defined hash
+    int anchor = 0, pnext = 0, op = 0;
+    for (int g0 = 0; g0 <= last_q; g0 += kGroup) {
+        uint32_t v[NC], v2[NC], cand[NC];
+        uint64_t m[NC];
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            const int p = g0 + cc * kChunk + lane;
+            const int pc = p < MAXB ? p : MAXB;
+            const uint32_t *d = b32 + (pc >> 2);
+            const uint32_t d0 = d[0], d1 = d[1], d2 = d[2];
+            v[cc] = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)(pc & 3));
+            v2[cc] = __builtin_amdgcn_alignbyte(d2, d1, (uint32_t)(pc & 3));
+        }
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            const int c0 = g0 + cc * kChunk;
+            cand[cc] = 0;
+            if (c0 <= last_q) {
+                const int p = c0 + lane;
+                const bool ins = p <= last_ins;
+                const uint32_t h = (v[cc] * kHashMult) >> (32 - kHashBits);
+                if (p <= last_q) cand[cc] = table[h];
+                // when every inserted position of the chunk holds the same 4
+                // bytes they share one entry: only the largest position writes
+                const uint32_t v0 = __builtin_amdgcn_readfirstlane(v[cc]);
+                const bool uni = __ballot(ins && v[cc] != v0) == 0;
+                const int last_lane = last_ins - c0 < kChunk - 1 ? last_ins - c0 : kChunk - 1;
+                if (ins && (!uni || lane == last_lane)) atomicMax(&table[h], (uint32_t)(p + 1));
+            }
+        }
+        // (branch-free so that the 24 reads of the group issue back to back:
+        // a lane without a candidate reads position 0 and is masked after)
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            const int p = g0 + cc * kChunk + lane;
+            const int c = cand[cc] != 0 ? (int)cand[cc] - 1 : 0;
+            const uint32_t *d = b32 + (c >> 2);
+            const uint32_t e0 = d[0], e1 = d[1], e2 = d[2];
+            const bool ok = (p <= last_take) & (cand[cc] != 0) &
+                            (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) == v[cc]) &
+                            (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) == v2[cc]);
+            m[cc] = __ballot(ok);
+        }
+
+        // Greedy parse of the matches that start inside this group.
+        for (;;) {
+            const int start = max(pnext, g0);
+            if (start > last_take || start >= g0 + kGroup) break;
+            int q = -1, c = 0;
+#pragma unroll
+            for (int w = 0; w < NC; ++w) {
+                const int wb = g0 + w * kChunk;
+                uint64_t mm = m[w];
+                if (start > wb) mm = start - wb >= kChunk ? 0 : (mm & (~0ull << (start - wb)));
+                if (q < 0 && mm) {
+                    const int bit = __builtin_ctzll(mm);
+                    q = wb + bit;
+                    c = __builtin_amdgcn_readlane((int)cand[w], bit) - 1;
+                }
+            }
+            if (q < 0) break;
+            const int L = __builtin_amdgcn_readfirstlane(
+                extend_match<MAXB>(b32, c, q, kMinTake, n - kLastLiterals - q));
+            op = emit(dst, op, b32, anchor, q - anchor, q - c, L, false);
+            pnext = q + L;
+            anchor = pnext;
+        }
+    }
+    op = emit(dst, op, b32, anchor, n - anchor, 0, 0, true);
+    return op;
+}
+
+// ---- sizes -> offsets -------------------------------------------------------
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *sh)
+{
+    // 256-thread inclusive scan helper storage: sh[256]
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int64_t x = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    return sh[t]; // inclusive
+}
+
+__device__ __forceinline__ void fail(int32_t *status)
+{
+    if (threadIdx.x == 0) atomicCAS(status, 0, BSG_ECORRUPT);
+}
+
+// Read an LZ4 length continuation (255-runs then a byte < 255) at ip, 64
+// bytes per step.  Returns false when the input ends first.
+__device__ __forceinline__ bool read_len_ext(const uint8_t *ci, int &ip, int iend, int &len)
+{
+    const int lane = threadIdx.x;
+    for (;;) {
+        const int pos = ip + lane;
+        const uint32_t v = pos < iend ? ci[pos] : 0u;
+        const uint64_t m = __ballot(v != 255u);
+        if (m == 0) {
+            len += 255 * kWave;
+            ip += kWave;
+            continue;
+        }
+        const int f = __builtin_ctzll(m);
+        if (ip + f >= iend) return false;
+        len += 255 * f + __shfl((int)v, f);
+        ip += f + 1;
+        return true;
+    }
+}
+
+// out[op, op + ll) = in[src, src + ll), 256 bytes per step, 4 per lane.
+// Every step reads before it writes; the caller guarantees op <= src so a
+// step never overwrites input a later step still has to read.
+__device__ __forceinline__ void lds_copy(uint8_t *b8, const uint32_t *b32, int op, int src, int ll)
+{
+    const int pos0 = 4 * (int)threadIdx.x;
+    const int mis = op & 3;
+    for (int k = 0; k < ll; k += 4 * kWave) {
+        const int pos = k + pos0;
+        if (pos < ll) {
+            const uint32_t v = lds_le32(b32, src + pos);
+            put4(b8, op + pos, v, ll - pos < 4 ? ll - pos : 4, mis);
+        }
+    }
+}
+
+// LZ4 match: out[op + i] = out[op - off + (i mod off)] for i < ml.  Every
+// source byte lies in [op - off, op), final before the match starts, so all
+// steps are independent; short periods (1..3) are replicated from registers.
+__device__ __forceinline__ void lds_match(uint8_t *b8, const uint32_t *b32, int op, int off, int ml)
+{
+    const int pos0 = 4 * (int)threadIdx.x;
+    const int mis = op & 3;
+    const int base = op - off;
+    if (off >= ml) { // no overlap
+        for (int k = 0; k < ml; k += 4 * kWave) {
+            const int pos = k + pos0;
+            if (pos < ml) put4(b8, op + pos, lds_le32(b32, base + pos), ml - pos < 4 ? ml - pos : 4, mis);
+        }
+        return;
+    }
+    if (off < 4) {
+        const uint32_t p0 = b8[base], p1 = b8[base + (off > 1 ? 1 : 0)], p2 = b8[base + (off > 2 ? 2 : 0)];
+        for (int k = 0; k < ml; k += 4 * kWave) {
+            const int pos = k + pos0;
+            if (pos >= ml) continue;
+            uint32_t v;
+            if (off == 1) {
+                v = p0 * 0x01010101u;
+            } else if (off == 2) { // pos is even
+                v = (p0 | (p1 << 8)) * 0x00010001u;
+            } else {
+                const int r = pos % 3;
+                const uint32_t a = r == 0 ? p0 : (r == 1 ? p1 : p2);
+                const uint32_t b = r == 0 ? p1 : (r == 1 ? p2 : p0);
+                const uint32_t c = r == 0 ? p2 : (r == 1 ? p0 : p1);
+                v = a | (b << 8) | (c << 16) | (a << 24);
+            }
+            put4(b8, op + pos, v, ml - pos < 4 ? ml - pos : 4, mis);
+        }
+        return;
+    }
+    // 4 <= off < ml: a period of off bytes
+    int r = pos0 % off;             // (k + pos0) mod off, advanced per step
+    const int step = (4 * kWave) % off;
+    for (int k = 0; k < ml; k += 4 * kWave) {
+        const int pos = k + pos0;
+        if (pos < ml) {
+            uint32_t v;
+            if (r + 3 < off) {
+                v = lds_le32(b32, base + r);
+            } else {
+                v = 0;
+                for (int j = 0; j < 4; ++j) {
+                    const int rj = r + j < off ? r + j : r + j - off;
+                    v |= (uint32_t)b8[base + rj] << (8 * j);
+                }
+            }
+            put4(b8, op + pos, v, ml - pos < 4 ? ml - pos : 4, mis);
+        }
+        r += step;
+        if (r >= off) r -= off;
+    }
+}
+
+// Decode the LZ4 block held at buf[ip0, iend) into buf[0, ob) in place (the
+// input sits at the tail of the buffer).  Returns false on malformed input:
+// every length, offset and the input/output boundaries are checked once per
+// sequence, and the output may never reach input not yet read.
+__device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend, int ob)
+{
+    uint8_t *b8 = reinterpret_cast<uint8_t *>(b32);
+    int ip = ip0, op = 0;
+    uint32_t w = __builtin_amdgcn_readfirstlane(lds_le32(b32, ip));
+    for (;;) {
+        if (ip >= iend) return false;
+        const uint32_t tok = w & 255u;
+        int ll = (int)(tok >> 4);
+        int lit = ip + 1;
+        if (ll == 15) {
+            const int e = (int)((w >> 8) & 255u);
+            if (ip + 1 >= iend) return false;
+            if (e != 255) {
+                ll += e;
+                lit = ip + 2;
+            } else {
+                int q = ip + 1;
+                if (!read_len_ext(b8, q, iend, ll)) return false;
+                lit = __builtin_amdgcn_readfirstlane(q);
+                ll = __builtin_amdgcn_readfirstlane(ll);
+            }
+        }
+        if (ll > iend - lit || ll > ob - op || op > lit) return false;
+        const int ip2 = lit + ll;
+        uint32_t ow = lds_le32(b32, ip2); // offset and first length byte
+        lds_copy(b8, b32, op, lit, ll);
+        op += ll;
+        if (ip2 == iend) break;
+        ow = __builtin_amdgcn_readfirstlane(ow);
+        if (iend - ip2 < 2) return false;
+        const int off = (int)(ow & 0xFFFFu);
+        int ml = (int)(tok & 15u) + kMinMatch;
+        int nip = ip2 + 2;
+        if ((tok & 15u) == 15u) {
+            if (nip >= iend) return false;
+            const int e = (int)((ow >> 16) & 255u);
+            if (e != 255) {
+                ml += e;
+                nip = ip2 + 3;
+            } else {
+                int q = ip2 + 2;
+                if (!read_len_ext(b8, q, iend, ml)) return false;
+                nip = __builtin_amdgcn_readfirstlane(q);
+                ml = __builtin_amdgcn_readfirstlane(ml);
+            }
+        }
+        if (off == 0 || off > op || ml > ob - op || op + ml > nip) return false;
+        w = lds_le32(b32, nip); // next token, read together with the match source
+        lds_match(b8, b32, op, off, ml);
+        w = __builtin_amdgcn_readfirstlane(w);
+        op += ml;
+        ip = nip;
+    }
+    return op == ob;
+}
+
+template <int E>
+__device__ __forceinline__ void unstage_fast(const uint8_t *lds, int64_t elems,
+                                             uint8_t *__restrict__ dst)
+{
+    const int64_t units = elems / Unit<E>::G;
+    for (int64_t u = threadIdx.x; u < units; u += kWave) {
+        uint32_t w[Unit<E>::IN_WORDS];
+        load_planes<E>(lds, elems / 8, u, w);
+        unit_inverse<E>(w);
+        store_unit<E>(dst + u * (Unit<E>::G * E), w);
+    }
+}
+
+template <int EC>
+__device__ __forceinline__ void unstage_block(const uint8_t *lds, int64_t elems, int64_t E,
+                                              uint8_t *__restrict__ dst, bool fast_out)
+{
+    if constexpr (EC != 0) {
+        if (fast_out && elems % Unit<EC>::G == 0) {
+            unstage_fast<EC>(lds, elems, dst);
+            return;
+        }
+    }
+    block_inverse_bits(lds, dst, elems, E);
+}
+
+// Bytes of the in-place LDS buffer for blocks up to MAXB bytes: the block
+// plus the slack a valid LZ4 block needs so that output never overtakes
+// unread input (any suffix of a block codes its output with at most
+// out/255 + 2 extra bytes), plus alignment.
+template <int MAXB> constexpr int dec_buf_bytes() { return (MAXB + MAXB / 255 + 64 + 3) & ~3; }
+
+
+// Copy sz bytes from a 16-byte aligned slot (readable for at least sz + 8
+// bytes) to any byte address: head bytes until dst is 4-byte aligned, then
+// aligned dword stores assembled from two source dwords, then tail bytes.
+__device__ __forceinline__ void copy_slot(uint8_t *__restrict__ dst, const uint8_t *__restrict__ src,
+                                          int sz)
+{
+    const int lane = threadIdx.x;
+    const int mis = (int)((4 - ((uintptr_t)dst & 3)) & 3);
+    const int head = mis < sz ? mis : sz;
+    if (lane < head) dst[lane] = src[lane];
+    const int body = (sz - head) / 4;
+    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);
+    uint32_t *d32 = reinterpret_cast<uint32_t *>(dst + head);
+    for (int w = lane; w < body; w += kWave) {
+        const int sp = head + 4 * w;
+        const uint32_t lo = s32[sp >> 2];
+        const uint32_t hi = s32[(sp >> 2) + 1];
+        d32[w] = __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)(sp & 3));
+    }
+    for (int i = head + 4 * body + lane; i < sz; i += kWave) dst[i] = src[i];
+}
+
+// ---- one block, start to end ----------------------------------------------
+template <int MAXB> struct EncLds {
+    uint32_t blk32[MAXB / 4 + 4];
+    uint32_t table[1 << kHashBits];
+};
+
+// Transpose (and optionally round) the elems x E bytes at src into LDS, then
+// LZ4-encode them into slot; returns the compressed size.  Leaves LDS free
+// for the next block.
+template <int MAXB, int EC, bool ROUND>
+__device__ __forceinline__ int encode_one(const uint8_t *__restrict__ src, int64_t elems, int64_t E,
+                                          const RoundParams &rp, int64_t first_elem,
+                                          uint8_t *__restrict__ slot, EncLds<MAXB> &L)
+{
+    stage_block<EC, ROUND>(src, elems, E, reinterpret_cast<uint8_t *>(L.blk32), rp, first_elem);
+    if (threadIdx.x < 4) L.blk32[MAXB / 4 + threadIdx.x] = 0;
+    __syncthreads();
+    const int sz = encode_block<MAXB>(L.blk32, (int)(elems * E), L.table, slot);
+    __syncthreads();
+    return sz;
+}
+
+template <int MAXB> struct DecLds {
+    uint32_t buf32[dec_buf_bytes<MAXB>() / 4 + 4]; // + over-read padding
+};
+
+// Decode block b of a stream (payload / off as laid out in the stream) into
+// dst (elems x E bytes).  Returns false when the block is corrupt; then dst
+// holds nothing meaningful.  Never reads past in_end.
+template <int MAXB, int EC>
+__device__ __forceinline__ bool decode_one(const uint8_t *__restrict__ payload, int64_t payload_len,
+                                           const uint64_t *__restrict__ off, int64_t b,
+                                           int64_t elems, int64_t E, const uint8_t *in_end,
+                                           uint8_t *__restrict__ dst, bool fast_out,
+                                           DecLds<MAXB> &L)
+{
+    constexpr int kBuf = dec_buf_bytes<MAXB>();
+    const int lane = threadIdx.x;
+    const int ob = (int)(elems * E);
+    const uint64_t o0 = off[b], o1 = off[b + 1];
+    if (o0 > o1 || o1 > (uint64_t)payload_len || o1 - o0 > (uint64_t)lz4_bound(ob)) return false;
+    const int len = (int)(o1 - o0);
+    // stage the LZ4 block at the tail of the buffer with the same 4-byte
+    // phase as in HBM: aligned dword copies, the last one possibly partial
+    const uint8_t *src = payload + o0;
+    const int s = (int)((uintptr_t)src & 3);
+    const int base = ((kBuf - len - s) & ~3) + s;
+    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src - s);
+    const int words = (s + len + 3) >> 2;
+    const int w0 = (base - s) >> 2;
+    for (int w = lane; w < words; w += kWave) {
+        const uint8_t *wp = reinterpret_cast<const uint8_t *>(s32 + w);
+        if (wp + 4 <= in_end) {
+            L.buf32[w0 + w] = s32[w];
+        } else {
+            uint32_t v = 0;
+            for (int k = 0; k < 4; ++k)
+                if (wp + k < in_end) v |= (uint32_t)wp[k] << (8 * k);
+            L.buf32[w0 + w] = v;
+        }
+    }
+    __syncthreads();
+    const bool ok = decode_inplace(L.buf32, base, base + len, ob);
+    __syncthreads();
+    if (ok) unstage_block<EC>(reinterpret_cast<const uint8_t *>(L.buf32), elems, E, dst, fast_out);
+    __syncthreads();
+    return ok;
+}
+
+// Header fields and offsets table ends of a stream agree with the expected
+// layout.  Called by one wavefront.
+__device__ __forceinline__ bool header_ok(const uint8_t *in, int64_t payload_len, int64_t n,
+                                          int64_t E, int64_t nb, int64_t n_blocks)
+{
+    const bsg_header *h = reinterpret_cast<const bsg_header *>(in);
+    const uint64_t *off = reinterpret_cast<const uint64_t *>(in + kHeaderBytes);
+    return h->magic == BSG_MAGIC && h->elem_size == (uint32_t)E && h->n == (uint64_t)n &&
+           h->block_elems == (uint32_t)nb && h->n_blocks == (uint32_t)n_blocks && off[0] == 0 &&
+           off[n_blocks] == (uint64_t)payload_len;
+}
+
+// The element class with a register fast path, or 0.
+inline int element_class(int64_t E) { return unit_elems(E) ? (int)E : 0; }
+
+} // namespace
+} // namespace bsg

@@ -68,3 +68,30 @@ def test_read_header(L):
     assert (h.magic, h.elem_size, h.n, h.block_elems, h.n_blocks) == (0x31475342, 4, 5000, 1024, 5)
     with pytest.raises(bsg.BsgError):
         bsg.read_header(b"\0" * 24)
+
+
+def test_batch_table_host_calls(L):
+    """Descriptor tables are built on the host: sizes, validation and the
+    workspace bound need no device."""
+    from paper_1503_00638_amd import _lib
+    assert L.bsg_batch_table_bytes(-1) == -1
+    t0, t3 = L.bsg_batch_table_bytes(0), L.bsg_batch_table_bytes(3)
+    assert 0 < t0 < t3
+    vp = ctypes.c_void_p
+    rows = [(4, 2048, 10000), (2, 0, 77), (8, 8192, 8192 * 2 + 5)]
+    arr = (_lib.Chunk * 3)(*[_lib.Chunk(vp(4096), 0, vp(8192), 1 << 20, n, e, b) for e, b, n in rows])
+    buf = ctypes.create_string_buffer(t3)
+    assert L.bsg_batch_build_table(arr, 3, buf, t3) == 0
+    assert L.bsg_batch_build_table(arr, 3, buf, t3 - 1) == -1
+    ws = L.bsg_batch_workspace_size(buf)
+    # workspace holds at least one bound-sized slot per block
+    import oracle
+    nblocks = sum((n // oracle.block_elems(e, b)) + 1 for e, b, n in rows)
+    assert ws >= sum(oracle.compress_bound(n, e, b) for e, b, n in rows) - 32 * 3
+    assert ws >= 4 * nblocks
+    bad = (_lib.Chunk * 1)(_lib.Chunk(vp(4096), 0, vp(8192), 1 << 20, 100, 4, 12))  # block % 8
+    assert L.bsg_batch_build_table(bad, 1, buf, t3) == -1
+    big = (_lib.Chunk * 1)(_lib.Chunk(vp(4096), 0, vp(8192), 1 << 20, 100, 8, 16384))  # 128 KiB
+    assert L.bsg_batch_build_table(big, 1, buf, t3) == -1
+    assert L.bsg_batch_compress(buf, None, vp(256), vp(256), 1 << 20, 0, None) == -1
+    assert L.bsg_batch_decompress(buf, vp(17), vp(256), 0, None) == -1
