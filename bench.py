@@ -88,16 +88,29 @@ def main(argv=None):
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale)")
+    ap.add_argument("--workload", choices=("chunk", "batch", "serve"), default="chunk",
+                    help="chunk: one 2.16 GB CHIME-shaped chunk (default); batch: 4096 "
+                         "independent chunks; serve: Poisson request stream")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path shards by "
-              "block ranges with no exchange, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): blocks, chunks and "
+              "requests are independent, so the path would shard by block ranges or whole "
+              "chunks with no exchange, but no multi-GPU run is part of this benchmark",
+              file=sys.stderr)
         return 2
 
     import torch
 
     import paper_1503_00638_amd as bsg
     from paper_1503_00638_amd import synth
+
+    if args.workload == "batch":
+        return bench_batch(args, torch, bsg)
+    if args.workload == "serve":
+        return bench_serve(args, torch, bsg)
 
     w = WORKLOAD
     dev = torch.device("cuda:0")
@@ -175,8 +188,8 @@ def main(argv=None):
 
     comp = float(np.mean(comp_ms))
     dcm = float(np.mean(dec_ms))
-    # algorithmic bytes (SURVEY-style accounting): rounding+compress
-    # reads U + autos and writes rU + offsets; decompress reads rU + offsets, writes U
+    # algorithmic bytes: rounding+compress reads U + autos and writes rU
+    # (offsets included); decompress reads rU and writes U
     n_blocks = -(-n // nb)
     table = 8 * (n_blocks + 1)
     bytes_comp = U + autos.nbytes + m
@@ -235,6 +248,198 @@ def main(argv=None):
     if not args.no_cpu:
         print("# timing the CPU oracle baseline", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(vis, autos, w, min(args.cpu_freqs, w["F"]))
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def _events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def _time_calls(torch, fn, steps, warmup):
+    """Per-call device times (ms) of fn on the current stream."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = _events(torch, steps + 1)
+    ev[0].record(stream)
+    for k in range(steps):
+        fn()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    return np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+
+
+def bench_batch(args, torch, bsg):
+    """Many independent chunks: the batch entry points (one persistent
+    kernel per element class, captured in a graph, launch shape autotuned)
+    against the plain per-chunk calls on the same buffers."""
+    from paper_1503_00638_amd import tune, workloads
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    specs, xs = workloads.make_batch(args.batch_count, device=dev)
+    torch.cuda.synchronize()
+    print(f"# generated {len(specs)} chunks in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    Es = [s.elem_size for s in specs]
+    Bs = [8192 // e for e in Es]
+    ns = [s.nbytes // s.elem_size for s in specs]
+    U = sum(s.nbytes for s in specs)
+
+    plan_c = bsg.BatchPlan.for_compress(xs, Es, Bs)
+    wc, tune_c = tune.tune(plan_c, "compress", use_cache=False)
+    nb = plan_c.compress(wc).cpu().numpy().copy()
+    assert (nb > 0).all()
+    plan_d = bsg.BatchPlan.for_decompress(plan_c.outs, nb.tolist(), ns, Es, Bs)
+    wd, tune_d = tune.tune(plan_d, "decompress", use_cache=False)
+    st = plan_d.decompress(wd)
+    torch.cuda.synchronize()
+    assert not st.any().item()
+    for x, y, s in zip(xs, plan_d.outs, specs):
+        assert torch.equal(x, y[: s.nbytes]), f"round trip mismatch in chunk {s.index}"
+    print(f"# tuned waves/CU: compress {wc}, decompress {wd}", file=sys.stderr, flush=True)
+
+    gc, gd = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(gc):
+        plan_c.compress(wc)
+    with torch.cuda.graph(gd):
+        plan_d.decompress(wd)
+    comp_ms = _time_calls(torch, gc.replay, args.steps, args.warmup)
+    dec_ms = _time_calls(torch, gd.replay, args.steps, args.warmup)
+    assert np.array_equal(plan_c.nbytes.cpu().numpy(), nb) and not plan_d.status.any().item()
+
+    # the plain per-chunk path on the same data (own output buffers)
+    outs = [torch.empty_like(o) for o in plan_c.outs]
+    ws = torch.empty(max(bsg.workspace_size(n, e, b) for n, e, b in zip(ns, Es, Bs)),
+                     dtype=torch.uint8, device=dev)
+    nbytes_pc = torch.empty(len(xs), dtype=torch.int64, device=dev)
+    status_pc = torch.zeros(len(xs), dtype=torch.int32, device=dev)
+    dec_pc = [torch.empty_like(o) for o in plan_d.outs]
+
+    def per_chunk_compress():
+        for k, x in enumerate(xs):
+            bsg.compress(x, Es[k], Bs[k], out=outs[k], workspace=ws, nbytes=nbytes_pc[k:k + 1])
+
+    def per_chunk_decompress():
+        for k in range(len(xs)):
+            bsg.decompress(outs[k], int(nb[k]), ns[k], Es[k], Bs[k], out=dec_pc[k],
+                           status=status_pc[k:k + 1])
+
+    pc_steps = max(1, min(args.steps, 3))
+    pcc_ms = _time_calls(torch, per_chunk_compress, pc_steps, 1)
+    pcd_ms = _time_calls(torch, per_chunk_decompress, pc_steps, 1)
+    assert np.array_equal(nbytes_pc.cpu().numpy(), nb), "per-chunk lengths differ from batch"
+    for k in range(len(xs)):
+        assert torch.equal(outs[k][: nb[k]], plan_c.outs[k][: nb[k]]), f"stream {k} differs"
+    assert not status_pc.any().item()
+    gpc_c, gpc_d = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gpc_c):
+        per_chunk_compress()
+    with torch.cuda.graph(gpc_d):
+        per_chunk_decompress()
+    gpcc_ms = _time_calls(torch, gpc_c.replay, pc_steps, 1)
+    gpcd_ms = _time_calls(torch, gpc_d.replay, pc_steps, 1)
+
+    C = float(nb.sum())
+    comp, dcm = float(np.median(comp_ms)), float(np.median(dec_ms))
+    gbps = lambda ms: round(U / (ms * 1e-3) / 1e9, 2)
+    enc_bytes, dec_bytes = U + C, C + U
+    dominant = ("k_batch_encode+scan+finish+pack (batch compress)", comp, enc_bytes) \
+        if comp >= dcm else ("k_batch_decode+k_batch_dec_tail (batch decompress)", dcm, dec_bytes)
+    achieved = dominant[2] / (dominant[1] * 1e-3) / 1e9
+    res = {
+        "metric": "uncompressed GB/s (compress & decompress) + % HBM peak; p50/p99 latency",
+        "value": round(U / ((comp + dcm) * 1e-3) / 1e9, 2),
+        "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(comp + dcm, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"batched: {len(xs)} independent chunks, sizes log-uniform "
+                               f"64 KiB-64 MiB (total {U / 2**30:.2f} GiB), elem_size in {{2,4,8}}, "
+                               "half noise-rounded visibilities, half int16 random walks, "
+                               "8192-byte blocks; batch compress then batch decompress, "
+                               "each one captured graph",
+                   "chunks": len(xs), "total_bytes": U, "parallelism": "single GPU"},
+        "compress_GBps": gbps(comp), "decompress_GBps": gbps(dcm),
+        "ratio": round(C / U, 5),
+        "hbm_frac_compress": round(enc_bytes / (comp * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "hbm_frac_decompress": round(dec_bytes / (dcm * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "latency_ms": {"compress_p50": round(float(np.percentile(comp_ms, 50)), 3),
+                       "compress_p99": round(float(np.percentile(comp_ms, 99)), 3),
+                       "decompress_p50": round(float(np.percentile(dec_ms, 50)), 3),
+                       "decompress_p99": round(float(np.percentile(dec_ms, 99)), 3)},
+        "autotune": {"waves_per_cu": {"compress": wc, "decompress": wd},
+                     "compress_ms": {str(k): round(v, 3) for k, v in tune_c.items()},
+                     "decompress_ms": {str(k): round(v, 3) for k, v in tune_d.items()}},
+        "per_chunk_eager": {"compress_GBps": gbps(float(np.median(pcc_ms))),
+                            "decompress_GBps": gbps(float(np.median(pcd_ms)))},
+        "per_chunk_graph": {"compress_GBps": gbps(float(np.median(gpcc_ms))),
+                            "decompress_GBps": gbps(float(np.median(gpcd_ms)))},
+        "roofline": {"bound": "hbm", "kernel": dominant[0], "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": int(dominant[2])},
+        "source_digest": source_digest(),
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_serve(args, torch, bsg):
+    """Poisson request stream over a device-resident payload pool: the
+    continuous-batching loop against the plain per-request path."""
+    from paper_1503_00638_amd import serve, synth, workloads
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    sizes = synth.gen_pool_sizes(256, seed=4)
+    pool = workloads.make_pool(sizes, device=dev)
+    for e in pool:  # every payload's stream decodes back to it
+        out, st = bsg.decompress(e.stream, e.stream_len, e.n, 4, workloads.POOL_BLOCK_ELEMS)
+        assert torch.equal(out[: e.nbytes], e.data) and int(st.item()) == 0
+    print(f"# pool of {len(pool)} payloads ({sum(sizes) / 2**30:.2f} GiB) in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    reqs = synth.gen_requests(args.serve_rate, args.serve_seconds, sizes, seed=5)
+    budget = 64 << 30
+    srv = serve.Server(pool, dev, hbm_budget=budget, n_streams=4, max_batch=64)
+    warm = [r for r in reqs[:300]]
+    srv.run(warm, "batch")
+    srv.run(warm, "single")
+    keep = {r.rid for r in reqs[::97]}
+    res_b, kept_b, nb_b = srv.run(reqs, "batch", keep)
+    print("# batched run done", file=sys.stderr, flush=True)
+    res_s, kept_s, nb_s = srv.run(reqs, "single", keep)
+    print("# per-request run done", file=sys.stderr, flush=True)
+    by_id = {r.rid: r for r in reqs}
+    for rid in keep:  # same bytes alone and in the mix, and equal to the pool
+        r, e = by_id[rid], pool[by_id[rid].payload]
+        (ob, xb), (os_, xs) = kept_b[rid], kept_s[rid]
+        if r.op == "compress":
+            m = int(xb.item())
+            assert m == int(xs.item()) == e.stream_len
+            assert torch.equal(ob[:m], os_[:m]) and torch.equal(ob[:m], e.stream)
+        else:
+            assert int(xb.item()) == 0 and int(xs.item()) == 0
+            assert torch.equal(ob[: e.nbytes], e.data) and torch.equal(os_[: e.nbytes], e.data)
+    sb, ss = serve.summarize(res_b, nb_b), serve.summarize(res_s, nb_s)
+    res = {
+        "metric": "uncompressed GB/s (compress & decompress) + % HBM peak; p50/p99 latency",
+        "value": sb["sustained_GBps"], "unit": "GB/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": len(warm), "ms_per_step": sb["latency_ms"]["mean"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals at {args.serve_rate:g}/s for "
+                               f"{args.serve_seconds:g} s, 60/40 decompress/compress, payloads of "
+                               "noise-rounded CHIME-shaped visibilities (float32 elements, "
+                               "8192-byte blocks), 256 KiB-256 MiB log-uniform, 64 GiB HBM "
+                               "budget, continuous batching on 4 streams",
+                   "pool_payloads": len(pool), "hbm_budget": budget,
+                   "parallelism": "single GPU"},
+        "batched": sb, "per_request": ss,
+        "source_digest": source_digest(),
+    }
     print(json.dumps(res), flush=True)
     return 0
 

@@ -206,92 +206,103 @@ def decompress_sync(s: torch.Tensor, n: int, elem_size: int, block_size: int = 0
 
 class BatchPlan:
     """Many chunks, each its own stream, compressed or decompressed by one
-    call of the batch C-ABI.  The plan builds the descriptor table (host and
-    device copies) and allocates every buffer once; compress() / decompress()
-    then only enqueue kernels, so they can be captured into a CUDA graph and
-    replayed.  Tensors referenced by the plan are kept alive by it."""
+    call of the batch C-ABI.  The plan builds the descriptor table (in pinned
+    host memory, copied asynchronously to the device on the plan's stream)
+    and allocates every buffer once, on that stream; compress() /
+    decompress() then only enqueue kernels, so they can be captured into a
+    CUDA graph and replayed.  Tensors referenced by the plan are kept alive
+    by it.  compress() / decompress() enqueue on the given stream, else the
+    current one; work on a stream other than the plan's must be ordered
+    after the plan's creation (the table copy)."""
 
-    def __init__(self, rows, device):
+    def __init__(self, rows, device, stream=None):
         L = _lib.lib()
         self.count = len(rows)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self._keep = [t for r in rows for t in (r[0], r[2]) if t is not None]
         arr = (_lib.Chunk * max(self.count, 1))()
         for k, (src, in_nbytes, dst, cap, n, e, b) in enumerate(rows):
             arr[k] = _lib.Chunk(src.data_ptr() if src is not None else None, in_nbytes,
                                 dst.data_ptr() if dst is not None else None, cap, n, e, b)
         tb = int(L.bsg_batch_table_bytes(self.count))
-        self._host = ctypes.create_string_buffer(tb)
+        self._host_t = torch.empty(tb, dtype=torch.uint8, pin_memory=True)
+        self._host = ctypes.c_void_p(self._host_t.data_ptr())
         _lib.check(L.bsg_batch_build_table(arr, self.count, self._host, tb), "batch_build_table")
-        self._dev = torch.frombuffer(bytearray(self._host.raw), dtype=torch.uint8).to(device)
+        with torch.cuda.stream(self.stream):
+            self._dev = torch.empty(tb, dtype=torch.uint8, device=device)
+            self._dev.copy_(self._host_t, non_blocking=True)
         self.device = device
 
+    @staticmethod
+    def _per_chunk(v, k):
+        return list(v) if isinstance(v, (list, tuple)) else [v] * k
+
     @classmethod
-    def for_compress(cls, inputs, elem_sizes, block_sizes=0, outs=None):
+    def for_compress(cls, inputs, elem_sizes, block_sizes=0, outs=None, stream=None):
         """inputs: device tensors (any dtype, contiguous) of whole elements;
         outs (optional): uint8 buffers, by default of compress_bound bytes."""
         k = len(inputs)
-        es = elem_sizes if isinstance(elem_sizes, (list, tuple)) else [elem_sizes] * k
-        bs = block_sizes if isinstance(block_sizes, (list, tuple)) else [block_sizes] * k
+        es, bs = cls._per_chunk(elem_sizes, k), cls._per_chunk(block_sizes, k)
         _require_device(*inputs)
         device = inputs[0].device if k else torch.device("cuda")
+        st = stream if stream is not None else torch.cuda.current_stream(device)
         rows, buf = [], []
-        for x, e, b in zip(inputs, es, bs):
-            if _nbytes(x) % e:
-                raise ValueError("buffer is not a whole number of elements")
-            n = _nbytes(x) // e
-            buf.append(torch.empty(compress_bound(n, e, b), dtype=torch.uint8, device=device)
-                       if outs is None else outs[len(buf)])
-            rows.append((x, 0, buf[-1], _nbytes(buf[-1]), n, e, b))
-        plan = cls(rows, device)
-        plan.outs = buf
-        ws = int(_lib.lib().bsg_batch_workspace_size(plan._host))
-        plan.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
-        plan.nbytes = torch.zeros(max(k, 1), dtype=torch.int64, device=device)
+        with torch.cuda.stream(st):
+            for x, e, b in zip(inputs, es, bs):
+                if _nbytes(x) % e:
+                    raise ValueError("buffer is not a whole number of elements")
+                n = _nbytes(x) // e
+                buf.append(torch.empty(compress_bound(n, e, b), dtype=torch.uint8, device=device)
+                           if outs is None else outs[len(buf)])
+                rows.append((x, 0, buf[-1], _nbytes(buf[-1]), n, e, b))
+            plan = cls(rows, device, st)
+            plan.outs = buf
+            plan.meta = [(r[4], r[5], r[6]) for r in rows]
+            ws = int(_lib.lib().bsg_batch_workspace_size(plan._host))
+            plan.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+            plan.nbytes = torch.zeros(max(k, 1), dtype=torch.int64, device=device)
         return plan
 
     @classmethod
-    def for_decompress(cls, streams, in_nbytes, ns, elem_sizes, block_sizes=0, outs=None):
+    def for_decompress(cls, streams, in_nbytes, ns, elem_sizes, block_sizes=0, outs=None,
+                       stream=None):
         """streams: device uint8 tensors holding the streams; in_nbytes their
         lengths; ns the element counts; outs (optional) the destinations."""
         k = len(streams)
-        es = elem_sizes if isinstance(elem_sizes, (list, tuple)) else [elem_sizes] * k
-        bs = block_sizes if isinstance(block_sizes, (list, tuple)) else [block_sizes] * k
+        es, bs = cls._per_chunk(elem_sizes, k), cls._per_chunk(block_sizes, k)
         _require_device(*streams)
         device = streams[0].device if k else torch.device("cuda")
+        st = stream if stream is not None else torch.cuda.current_stream(device)
         rows, buf = [], []
-        for s, m, n, e, b in zip(streams, in_nbytes, ns, es, bs):
-            buf.append(torch.empty(max(n * e, 1), dtype=torch.uint8, device=device)
-                       if outs is None else outs[len(buf)])
-            rows.append((s, int(m), buf[-1], 0, int(n), e, b))
-        plan = cls(rows, device)
-        plan.outs = buf
-        plan.status = torch.zeros(max(k, 1), dtype=torch.int32, device=device)
+        with torch.cuda.stream(st):
+            for s, m, n, e, b in zip(streams, in_nbytes, ns, es, bs):
+                buf.append(torch.empty(max(n * e, 1), dtype=torch.uint8, device=device)
+                           if outs is None else outs[len(buf)])
+                rows.append((s, int(m), buf[-1], 0, int(n), e, b))
+            plan = cls(rows, device, st)
+            plan.outs = buf
+            plan.meta = [(r[4], r[5], r[6]) for r in rows]
+            plan.status = torch.zeros(max(k, 1), dtype=torch.int32, device=device)
         return plan
 
     def compress(self, waves_per_cu: int = 0, stream=None) -> torch.Tensor:
         """Enqueue; returns the device int64 stream lengths (caller's order)."""
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
         _lib.check(_lib.lib().bsg_batch_compress(self._host, _ptr(self._dev), _ptr(self.nbytes),
                                                   _ptr(self.workspace), _nbytes(self.workspace),
-                                                  waves_per_cu, _stream_ptr(stream)),
+                                                  waves_per_cu, _stream_ptr(st)),
                    "batch_compress")
         return self.nbytes
 
     def decompress(self, waves_per_cu: int = 0, stream=None) -> torch.Tensor:
         """Enqueue; returns the device int32 per-chunk status (0 = ok)."""
-        with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.stream(st):
             self.status.zero_()
         _lib.check(_lib.lib().bsg_batch_decompress(self._host, _ptr(self._dev), _ptr(self.status),
-                                                    waves_per_cu, _stream_ptr(stream)),
+                                                    waves_per_cu, _stream_ptr(st)),
                    "batch_decompress")
         return self.status
-
-
-class _nullctx:
-    def __enter__(self):
-        return None
-
-    def __exit__(self, *a):
-        return False
 
 
 def read_header(host_bytes: bytes) -> Header:

@@ -168,6 +168,64 @@ def gen_chunk_vis(spec: ChunkSpec, vis_inputs: int = 16, T: int = 32):
 
 
 # ---------------------------------------------------------------------------
+# device-side generators (torch RNG on the GPU) for the large workloads
+# ---------------------------------------------------------------------------
+# The same models as above, drawn with torch's device generator so that tens
+# of GiB are produced in seconds.  Bit patterns differ from the numpy
+# generators (a different RNG), the distributions are the same.  A check
+# against the oracle copies the generated raw input to the host.
+
+def gen_vis_device(F: int, I: int, T: int, seed: int, n_samples: float = N_SAMPLES_DEFAULT,
+                   device="cuda"):
+    """(vis complex64 (F, P, T), autos float32 (F, I, T)) on the device."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(int(seed))
+    f64 = torch.float64
+    phi = torch.rand(I, generator=g, device=device, dtype=f64)
+    psi = torch.rand(I, generator=g, device=device, dtype=f64)
+    f = torch.arange(F, device=device, dtype=f64)[:, None, None]
+    t = torch.arange(T, device=device, dtype=f64)[None, None, :]
+    A = 1e3 * (1.0 + 0.2 * torch.sin(2 * math.pi * (f / F + phi[None, :, None]))) * \
+        (1.0 + 0.02 * torch.sin(2 * math.pi * (t / T + psi[None, :, None])))
+    pairs = torch.from_numpy(product_pairs(I)).to(device=device, dtype=torch.long)
+    ii, jj = pairs[:, 0], pairs[:, 1]
+    is_auto = ii == jj
+    z = torch.randn((F, pairs.shape[0], T, 2), generator=g, device=device, dtype=torch.float32)
+    sig = torch.sqrt(A[:, ii] * A[:, jj] * (0.5 / n_samples)).to(torch.float32)
+    vf = z * sig[..., None]
+    del sig
+    Aa = A[:, ii[is_auto]]
+    vf[:, is_auto, :, 0] = (Aa + Aa * (1.0 / math.sqrt(n_samples)) * z[:, is_auto, :, 0]).to(torch.float32)
+    vf[:, is_auto, :, 1] = 0.0
+    del z
+    autos = vf[:, is_auto, :, 0].contiguous()
+    return torch.view_as_complex(vf), autos
+
+
+def gen_walk_device(n: int, seed: int, device="cuda"):
+    """int16 random walk from 0 (steps uniform in [-8, 8], wraparound)."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(int(seed))
+    steps = torch.randint(-8, 9, (n,), generator=g, device=device, dtype=torch.int32)
+    w = torch.cumsum(steps, 0, dtype=torch.int32)
+    return (((w + 32768) & 0xFFFF) - 32768).to(torch.int16)
+
+
+def gen_chunk_vis_device(spec: ChunkSpec, vis_inputs: int = 16, T: int = 32, device="cuda"):
+    """Device (vis, autos) covering at least spec.nbytes bytes of complex64."""
+    per_f = n_products(vis_inputs) * T * 8
+    F = max(1, -(-spec.nbytes // per_f))
+    return gen_vis_device(F, vis_inputs, T, spec.seed, device=device)
+
+
+def gen_walk_chunk_device(spec: ChunkSpec, device="cuda"):
+    """Device uint8 tensor of spec.nbytes bytes of int16 random walk."""
+    import torch
+    w = gen_walk_device((spec.nbytes + 1) // 2, spec.seed, device)
+    return w.view(torch.uint8)[: spec.nbytes]
+
+
+# ---------------------------------------------------------------------------
 # serving requests
 # ---------------------------------------------------------------------------
 
@@ -176,25 +234,34 @@ class Request:
     rid: int
     t_arrival: float  # seconds from start
     op: str  # "compress" | "decompress"
-    nbytes: int
-    payload: int  # index into a payload pool
+    payload: int  # index into the payload pool
+    nbytes: int  # uncompressed bytes (the payload's size)
 
 
-def gen_requests(rate_hz: float, duration_s: float, seed: int = 4, lo: int = 1 << 18,
-                 hi: int = 1 << 28, p_decompress: float = 0.6, n_payloads: int = 64,
-                 elem_size: int = 4) -> list[Request]:
-    """Poisson arrivals, log-uniform sizes rounded to whole elements."""
+def gen_pool_sizes(count: int = 256, seed: int = 4, lo: int = 1 << 18, hi: int = 1 << 28,
+                   elem_size: int = 4) -> list[int]:
+    """Payload sizes log-uniform in [lo, hi) bytes, whole elements."""
+    rng = _rng(seed)
+    out = []
+    for _ in range(count):
+        nb = int(math.exp(rng.uniform(math.log(lo), math.log(hi))))
+        out.append(nb - nb % elem_size)
+    return out
+
+
+def gen_requests(rate_hz: float, duration_s: float, pool_sizes: list[int], seed: int = 5,
+                 p_decompress: float = 0.6) -> list[Request]:
+    """Poisson arrivals at rate_hz for duration_s; each request names a
+    payload of the pool uniformly at random (so sizes follow the pool's
+    log-uniform law) and is a decompression with probability p_decompress."""
     rng = _rng(seed)
     t = 0.0
     out = []
-    rid = 0
     while True:
         t += rng.exponential(1.0 / rate_hz)
         if t >= duration_s:
             break
-        nb = int(math.exp(rng.uniform(math.log(lo), math.log(hi))))
-        nb -= nb % elem_size
         op = "decompress" if rng.random() < p_decompress else "compress"
-        out.append(Request(rid, t, op, nb, int(rng.integers(0, n_payloads))))
-        rid += 1
+        k = int(rng.integers(0, len(pool_sizes)))
+        out.append(Request(len(out), t, op, k, pool_sizes[k]))
     return out
