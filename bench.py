@@ -88,9 +88,10 @@ def main(argv=None):
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale)")
-    ap.add_argument("--workload", choices=("chunk", "batch", "serve"), default="chunk",
+    ap.add_argument("--workload", choices=("chunk", "batch", "serve", "sweep"), default="chunk",
                     help="chunk: one 2.16 GB CHIME-shaped chunk (default); batch: 4096 "
-                         "independent chunks; serve: Poisson request stream")
+                         "independent chunks; serve: Poisson request stream; sweep: bit "
+                         "transpose of 1 GiB at every element size and block size")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -111,6 +112,8 @@ def main(argv=None):
         return bench_batch(args, torch, bsg)
     if args.workload == "serve":
         return bench_serve(args, torch, bsg)
+    if args.workload == "sweep":
+        return bench_sweep(args, torch, bsg)
 
     w = WORKLOAD
     dev = torch.device("cuda:0")
@@ -194,10 +197,15 @@ def main(argv=None):
     table = 8 * (n_blocks + 1)
     bytes_comp = U + autos.nbytes + m
     bytes_dec = m + U
-    dominant, dom_ms, dom_bytes = ("k_encode+scan+pack (round_compress)", comp, bytes_comp) \
-        if comp >= dcm else ("k_decode (decompress)", dcm, bytes_dec)
+    if comp >= dcm:
+        dominant, dom_ms, dom_bytes, tkey = (
+            "round_compress call: k_encode<8192,4,true> + k_tile_sum + k_tile_offsets + "
+            "k_write_offsets + k_pack", comp, bytes_comp, "round_compress_call")
+    else:
+        dominant, dom_ms, dom_bytes, tkey = ("decompress call: k_decode<8192,4>", dcm, bytes_dec,
+                                             "decompress_call")
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = traffic_for("k_decode" if dominant.startswith("k_decode") else "k_encode")
+    traffic = traffic_for(tkey)
     value = U * args.steps / (float(np.sum(step_ms)) * 1e-3) / 1e9
 
     res = {
@@ -381,6 +389,62 @@ def bench_batch(args, torch, bsg):
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                      "algorithmic_bytes_per_launch": int(dominant[2])},
+        "source_digest": source_digest(),
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_sweep(args, torch, bsg):
+    """Bit transpose only, 1 GiB per call: forward and inverse at element
+    sizes 1/2/4/8/16 and block sizes of 2048/8192/65536 bytes.  Each call
+    reads and writes 1 GiB (2 GiB of HBM traffic)."""
+    dev = torch.device("cuda:0")
+    nbytes = 1 << 30
+    g = torch.Generator(device=dev).manual_seed(2)
+    x = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device=dev, generator=g)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    rows = []
+    for E in (1, 2, 4, 8, 16):
+        for bb in (2048, 8192, 65536):
+            nb = bb // E
+            fwd = _time_calls(torch, lambda: bsg.bitshuffle(x, E, nb, out=y), args.steps,
+                              args.warmup)
+            inv = _time_calls(torch, lambda: bsg.bitunshuffle(y, E, nb, out=z), args.steps,
+                              args.warmup)
+            torch.cuda.synchronize()
+            assert torch.equal(x, z), (E, bb)
+            f, i = float(np.median(fwd)), float(np.median(inv))
+            rows.append({"elem_size": E, "block_bytes": bb,
+                         "forward_GBps": round(nbytes / (f * 1e-3) / 1e9, 1),
+                         "inverse_GBps": round(nbytes / (i * 1e-3) / 1e9, 1),
+                         "forward_hbm_frac": round(2 * nbytes / (f * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                         "inverse_hbm_frac": round(2 * nbytes / (i * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)})
+    # a plain device-to-device copy of the same size: the achievable ceiling
+    cp = float(np.median(_time_calls(torch, lambda: z.copy_(x), args.steps, args.warmup)))
+    copy_gbps = 2 * nbytes / (cp * 1e-3) / 1e9
+    best = max(rows, key=lambda r: r["forward_GBps"])
+    worst = min(rows, key=lambda r: min(r["forward_GBps"], r["inverse_GBps"]))
+    res = {
+        "metric": "uncompressed GB/s (compress & decompress) + % HBM peak; p50/p99 latency",
+        "value": round(float(np.median([min(r["forward_GBps"], r["inverse_GBps"]) for r in rows])), 1),
+        "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "bit-transpose sweep: 1 GiB of uniform random bytes per call, "
+                               "elem_size 1/2/4/8/16 x block 2048/8192/65536 bytes, "
+                               "bitshuffle and bitunshuffle (value: median over the 15 cases "
+                               "of the slower direction)",
+                   "parallelism": "single GPU"},
+        "cases": rows,
+        "copy_hbm_GBps": round(copy_gbps, 1),
+        "roofline": {"bound": "hbm", "kernel": f"bitshuffle E={best['elem_size']} "
+                                               f"B={best['block_bytes']}",
+                     "achieved": round(2 * best["forward_GBps"], 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": best["forward_hbm_frac"], "traffic": None,
+                     "algorithmic_bytes_per_launch": 2 * nbytes},
+        "slowest_case": worst,
         "source_digest": source_digest(),
     }
     print(json.dumps(res), flush=True)
