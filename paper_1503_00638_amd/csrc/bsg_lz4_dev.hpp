@@ -361,67 +361,92 @@ __device__ __forceinline__ bool read_len_ext(const uint8_t *ci, int &ip, int ien
     }
 }
 
-// out[op, op + ll) = in[src, src + ll), 256 bytes per step, 4 per lane.
-// Every step reads before it writes; the caller guarantees op <= src so a
-// step never overwrites input a later step still has to read.
-__device__ __forceinline__ void lds_copy(uint8_t *b8, const uint32_t *b32, int op, int src, int ll)
+// Copies of the in-place decoder, aligned on the destination: the output
+// bytes [op, op + len) are covered by whole dwords [op / 4, (op + len + 3) / 4),
+// and each lane builds one dword per step from its source bytes and writes it
+// with one aligned store.  Bytes of the first and last dword outside the
+// range keep their old value (final output below, or input not yet read
+// above: rewritten unchanged).  Sources may lie up to 3 bytes before b32[0],
+// so the buffer has a padding dword in front.
+__device__ __forceinline__ uint32_t range_mask(int d, int op, int end)
 {
-    const int pos0 = 4 * (int)threadIdx.x;
-    const int mis = op & 3;
-    for (int k = 0; k < ll; k += 4 * kWave) {
-        const int pos = k + pos0;
-        if (pos < ll) {
-            const uint32_t v = lds_le32(b32, src + pos);
-            put4(b8, op + pos, v, ll - pos < 4 ? ll - pos : 4, mis);
+    const int lo = op - d > 0 ? op - d : 0; // 0..3
+    const int hi = end - d < 4 ? end - d : 4; // 1..4
+    const uint32_t mhi = hi >= 4 ? 0xFFFFFFFFu : ((1u << (8 * hi)) - 1u);
+    return mhi & ~((1u << (8 * lo)) - 1u);
+}
+
+__device__ __forceinline__ void put_word(uint32_t *b32, int w, uint32_t v, int op, int end)
+{
+    const uint32_t m = range_mask(4 * w, op, end);
+    if (m != 0xFFFFFFFFu) v = (v & m) | (b32[w] & ~m);
+    b32[w] = v;
+}
+
+// out[op, op + len) = buf[src, src + len) for src >= op (literals: every step
+// reads before it writes, and a later step never reads a dword an earlier
+// step wrote) or src + len <= op (a match without overlap).
+__device__ __forceinline__ void dcopy(uint32_t *b32, int op, int src, int len)
+{
+    const int w0 = op >> 2, w1 = (op + len + 3) >> 2, end = op + len;
+    const int delta = src - op;
+    const uint32_t sh = (uint32_t)(delta & 3);
+    for (int b = w0; b < w1; b += kWave) {
+        const int w = b + (int)threadIdx.x;
+        if (w < w1) {
+            const int a = (4 * w + delta) >> 2;
+            put_word(b32, w, __builtin_amdgcn_alignbyte(b32[a + 1], b32[a], sh), op, end);
         }
     }
 }
 
-// LZ4 match: out[op + i] = out[op - off + (i mod off)] for i < ml.  Every
+// LZ4 match: out[op + i] = out[op - off + (i mod off)] for i < len.  Every
 // source byte lies in [op - off, op), final before the match starts, so all
-// steps are independent; short periods (1..3) are replicated from registers.
-__device__ __forceinline__ void lds_match(uint8_t *b8, const uint32_t *b32, int op, int off, int ml)
+// steps are independent.  Lane state r = (byte offset of its dword from op)
+// mod off, advanced by 256 mod off per step.
+__device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
 {
-    const int pos0 = 4 * (int)threadIdx.x;
-    const int mis = op & 3;
+    if (off >= len) {
+        dcopy(b32, op, op - off, len);
+        return;
+    }
+    const uint8_t *b8 = reinterpret_cast<const uint8_t *>(b32);
+    const int w0 = op >> 2, w1 = (op + len + 3) >> 2, end = op + len;
     const int base = op - off;
-    if (off >= ml) { // no overlap
-        for (int k = 0; k < ml; k += 4 * kWave) {
-            const int pos = k + pos0;
-            if (pos < ml) put4(b8, op + pos, lds_le32(b32, base + pos), ml - pos < 4 ? ml - pos : 4, mis);
-        }
-        return;
-    }
-    if (off < 4) {
-        const uint32_t p0 = b8[base], p1 = b8[base + (off > 1 ? 1 : 0)], p2 = b8[base + (off > 2 ? 2 : 0)];
-        for (int k = 0; k < ml; k += 4 * kWave) {
-            const int pos = k + pos0;
-            if (pos >= ml) continue;
-            uint32_t v;
-            if (off == 1) {
-                v = p0 * 0x01010101u;
-            } else if (off == 2) { // pos is even
-                v = (p0 | (p1 << 8)) * 0x00010001u;
-            } else {
-                const int r = pos % 3;
-                const uint32_t a = r == 0 ? p0 : (r == 1 ? p1 : p2);
-                const uint32_t b = r == 0 ? p1 : (r == 1 ? p2 : p0);
-                const uint32_t c = r == 0 ? p2 : (r == 1 ? p0 : p1);
-                v = a | (b << 8) | (c << 16) | (a << 24);
-            }
-            put4(b8, op + pos, v, ml - pos < 4 ? ml - pos : 4, mis);
-        }
-        return;
-    }
-    // 4 <= off < ml: a period of off bytes
-    int r = pos0 % off;             // (k + pos0) mod off, advanced per step
+    int r = (4 * (w0 + (int)threadIdx.x) - op + 4 * off) % off;
     const int step = (4 * kWave) % off;
-    for (int k = 0; k < ml; k += 4 * kWave) {
-        const int pos = k + pos0;
-        if (pos < ml) {
+    if (off < 4) { // a period of 1..3 bytes, replicated from registers
+        const uint32_t p0 = b8[base], p1 = b8[base + (off > 1 ? 1 : 0)],
+                       p2 = b8[base + (off > 2 ? 2 : 0)];
+        for (int b = w0; b < w1; b += kWave) {
+            const int w = b + (int)threadIdx.x;
+            if (w < w1) {
+                uint32_t v;
+                if (off == 1) {
+                    v = p0 * 0x01010101u;
+                } else if (off == 2) {
+                    v = (r == 0 ? (p0 | (p1 << 8)) : (p1 | (p0 << 8))) * 0x00010001u;
+                } else {
+                    const uint32_t a = r == 0 ? p0 : (r == 1 ? p1 : p2);
+                    const uint32_t c1 = r == 0 ? p1 : (r == 1 ? p2 : p0);
+                    const uint32_t c2 = r == 0 ? p2 : (r == 1 ? p0 : p1);
+                    v = a | (c1 << 8) | (c2 << 16) | (a << 24);
+                }
+                put_word(b32, w, v, op, end);
+            }
+            r += step;
+            if (r >= off) r -= off;
+        }
+        return;
+    }
+    for (int b = w0; b < w1; b += kWave) {
+        const int w = b + (int)threadIdx.x;
+        if (w < w1) {
             uint32_t v;
             if (r + 3 < off) {
-                v = lds_le32(b32, base + r);
+                const int sidx = base + r;
+                v = __builtin_amdgcn_alignbyte(b32[(sidx >> 2) + 1], b32[sidx >> 2],
+                                               (uint32_t)(sidx & 3));
             } else {
                 v = 0;
                 for (int j = 0; j < 4; ++j) {
@@ -429,7 +454,7 @@ __device__ __forceinline__ void lds_match(uint8_t *b8, const uint32_t *b32, int 
                     v |= (uint32_t)b8[base + rj] << (8 * j);
                 }
             }
-            put4(b8, op + pos, v, ml - pos < 4 ? ml - pos : 4, mis);
+            put_word(b32, w, v, op, end);
         }
         r += step;
         if (r >= off) r -= off;
@@ -440,12 +465,19 @@ __device__ __forceinline__ void lds_match(uint8_t *b8, const uint32_t *b32, int 
 // input sits at the tail of the buffer).  Returns false on malformed input:
 // every length, offset and the input/output boundaries are checked once per
 // sequence, and the output may never reach input not yet read.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 __device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend, int ob)
 {
     uint8_t *b8 = reinterpret_cast<uint8_t *>(b32);
-    int ip = ip0, op = 0;
+    int ip = uni(ip0), op = 0;
+    iend = uni(iend);
+    ob = uni(ob);
     uint32_t w = __builtin_amdgcn_readfirstlane(lds_le32(b32, ip));
     for (;;) {
+        ip = uni(ip);
+        op = uni(op);
+        w = (uint32_t)uni((int)w);
         if (ip >= iend) return false;
         const uint32_t tok = w & 255u;
         int ll = (int)(tok >> 4);
@@ -458,15 +490,18 @@ __device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend,
                 lit = ip + 2;
             } else {
                 int q = ip + 1;
-                if (!read_len_ext(b8, q, iend, ll)) return false;
-                lit = __builtin_amdgcn_readfirstlane(q);
-                ll = __builtin_amdgcn_readfirstlane(ll);
+                const int okl = uni(read_len_ext(b8, q, iend, ll) ? 1 : 0);
+                if (!okl) return false;
+                lit = uni(q);
+                ll = uni(ll);
             }
         }
+        ll = uni(ll);
+        lit = uni(lit);
         if (ll > iend - lit || ll > ob - op || op > lit) return false;
         const int ip2 = lit + ll;
         uint32_t ow = lds_le32(b32, ip2); // offset and first length byte
-        lds_copy(b8, b32, op, lit, ll);
+        dcopy(b32, op, lit, ll);
         op += ll;
         if (ip2 == iend) break;
         ow = __builtin_amdgcn_readfirstlane(ow);
@@ -482,14 +517,17 @@ __device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend,
                 nip = ip2 + 3;
             } else {
                 int q = ip2 + 2;
-                if (!read_len_ext(b8, q, iend, ml)) return false;
-                nip = __builtin_amdgcn_readfirstlane(q);
-                ml = __builtin_amdgcn_readfirstlane(ml);
+                const int okm = uni(read_len_ext(b8, q, iend, ml) ? 1 : 0);
+                if (!okm) return false;
+                nip = uni(q);
+                ml = uni(ml);
             }
         }
+        ml = uni(ml);
+        nip = uni(nip);
         if (off == 0 || off > op || ml > ob - op || op + ml > nip) return false;
         w = lds_le32(b32, nip); // next token, read together with the match source
-        lds_match(b8, b32, op, off, ml);
+        dmatch(b32, op, off, ml);
         w = __builtin_amdgcn_readfirstlane(w);
         op += ml;
         ip = nip;
@@ -575,7 +613,7 @@ __device__ __forceinline__ int encode_one(const uint8_t *__restrict__ src, int64
 }
 
 template <int MAXB> struct DecLds {
-    uint32_t buf32[dec_buf_bytes<MAXB>() / 4 + 4]; // + over-read padding
+    uint32_t buf32[dec_buf_bytes<MAXB>() / 4 + 8]; // + a padding dword in front, over-read after
 };
 
 // Decode block b of a stream (payload / off as laid out in the stream) into
@@ -602,21 +640,22 @@ __device__ __forceinline__ bool decode_one(const uint8_t *__restrict__ payload, 
     const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src - s);
     const int words = (s + len + 3) >> 2;
     const int w0 = (base - s) >> 2;
+    uint32_t *B = L.buf32 + 4; // the decode buffer; B[-1] is readable padding
     for (int w = lane; w < words; w += kWave) {
         const uint8_t *wp = reinterpret_cast<const uint8_t *>(s32 + w);
         if (wp + 4 <= in_end) {
-            L.buf32[w0 + w] = s32[w];
+            B[w0 + w] = s32[w];
         } else {
             uint32_t v = 0;
             for (int k = 0; k < 4; ++k)
                 if (wp + k < in_end) v |= (uint32_t)wp[k] << (8 * k);
-            L.buf32[w0 + w] = v;
+            B[w0 + w] = v;
         }
     }
     __syncthreads();
-    const bool ok = decode_inplace(L.buf32, base, base + len, ob);
+    const bool ok = decode_inplace(B, base, base + len, ob);
     __syncthreads();
-    if (ok) unstage_block<EC>(reinterpret_cast<const uint8_t *>(L.buf32), elems, E, dst, fast_out);
+    if (ok) unstage_block<EC>(reinterpret_cast<const uint8_t *>(B), elems, E, dst, fast_out);
     __syncthreads();
     return ok;
 }
