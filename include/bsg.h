@@ -89,6 +89,25 @@ int bsg_round_to_noise(const void *vis_in, void *vis_out, const float *autos, in
                        int64_t I, int64_t T, const int32_t *prod_map, double n_samples,
                        double f, void *stream);
 
+/* Integer visibilities, the correlator's own data type (Section 5): the
+ * same noise-relative rounding on int32 values.
+ * vis_in / vis_out: int32 [F][P][T][2] (re, im), 8-byte aligned; may alias.
+ * autos: int32 [F][I][T], the measured auto-correlations (real parts of
+ *   the auto products before rounding); must not overlap vis_out.
+ * G2 = (V_ii V_jj as an exact int64, rounded once to double) c for crosses,
+ *   (V_ii^2 likewise) 2c for autos, c = (12 f) / (2 N); k = the largest
+ *   integer with 4^k < G2.  Every integer is a multiple of 2^k for k <= 0,
+ *   so only k >= 1 changes a value: re and im go to the nearest multiple of
+ *   2^k, ties to the even multiple, computed in exact integer arithmetic; a
+ *   result above INT32_MAX becomes the largest multiple of 2^k that fits.
+ *   The imaginary part of an auto is copied; G2 not positive and finite
+ *   leaves the element unchanged.
+ * Errors as bsg_round_to_noise.  A stream of the rounded values is made by
+ * bsg_compress_lz4 with elem_size 8 (one complex value per element). */
+int bsg_round_to_noise_i32(const void *vis_in, void *vis_out, const int32_t *autos, int64_t F,
+                           int64_t I, int64_t T, const int32_t *prod_map, double n_samples,
+                           double f, void *stream);
+
 /* ---- Stage 2a: bit transpose within blocks (Section 4.2) --------------
  * in, out: n elements of elem_size bytes; must not overlap.
  * Bit b = 8 * (byte within element) + (bit within byte, LSB = 0) of element

@@ -48,6 +48,10 @@ def lib():
         L.oracle_granularity_exponent.restype = i32
         L.oracle_round_to_multiple.argtypes = [ctypes.c_float, i32]
         L.oracle_round_to_multiple.restype = ctypes.c_float
+        L.oracle_round_int_to_multiple.argtypes = [ctypes.c_int32, i32]
+        L.oracle_round_int_to_multiple.restype = ctypes.c_int32
+        L.oracle_round_to_noise_i32.argtypes = [vp, vp, vp, i64, i64, i64, vp, dbl, dbl, i32]
+        L.oracle_round_to_noise_i32.restype = i32
         for name in ("oracle_bitshuffle", "oracle_bitunshuffle"):
             getattr(L, name).argtypes = [vp, vp, i64, i64, i64, i32]
             getattr(L, name).restype = i32
@@ -110,6 +114,27 @@ def round_to_noise(vis: np.ndarray, autos: np.ndarray, n_samples: float, f: floa
                                      float(n_samples), float(f), int(nthreads))
     if rc != 0:
         raise OracleError(rc, "round_to_noise")
+    return out
+
+
+def round_int_to_multiple(x: int, k: int) -> int:
+    return int(lib().oracle_round_int_to_multiple(int(x), int(k)))
+
+
+def round_to_noise_i32(vis: np.ndarray, autos: np.ndarray, n_samples: float, f: float,
+                       prod_map: np.ndarray | None = None, nthreads: int = 0) -> np.ndarray:
+    """vis int32 (F, P, T, 2), autos int32 (F, I, T) -> rounded copy of vis."""
+    vis = np.ascontiguousarray(vis, dtype=np.int32)
+    autos = np.ascontiguousarray(autos, dtype=np.int32)
+    F, I, T = autos.shape
+    if vis.shape != (F, I * (I + 1) // 2, T, 2):
+        raise ValueError(f"vis shape {vis.shape} does not match autos {autos.shape}")
+    out = np.empty_like(vis)
+    pm = None if prod_map is None else np.ascontiguousarray(prod_map, dtype=np.int32)
+    rc = lib().oracle_round_to_noise_i32(_ptr(vis), _ptr(out), _ptr(autos), F, I, T, _ptr(pm),
+                                         float(n_samples), float(f), int(nthreads))
+    if rc != 0:
+        raise OracleError(rc, "round_to_noise_i32")
     return out
 
 

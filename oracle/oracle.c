@@ -147,6 +147,107 @@ int oracle_round_to_noise(const float *vis_in, float *vis_out, const float *auto
     return 0;
 }
 
+/* ----------------------------------------------------------------------
+ * Integer visibilities (the data type of the paper's own evaluation,
+ * Section 5): re and im are int32.  Every integer is already a multiple of
+ * g = 1, so only k >= 1 changes anything (g <= 1 means no rounding).
+ * ---------------------------------------------------------------------- */
+
+/* Nearest multiple of 2^k to x, ties to the even multiple, in exact integer
+ * arithmetic.  A result above INT32_MAX (only x near INT32_MAX rounding up)
+ * becomes the largest multiple of 2^k that fits; the negative side always
+ * fits because -2^31 is a multiple of every 2^k with k <= 31. */
+int32_t oracle_round_int_to_multiple(int32_t x, int k)
+{
+    if (k <= 0)
+        return x;
+    if (k > 62) /* |x| <= 2^31 < g/2: the nearest multiple is zero */
+        k = 62;
+    const int64_t g = (int64_t)1 << k;
+    int64_t q = (int64_t)x / g, rem = (int64_t)x % g; /* C truncates toward zero */
+    if (rem < 0) {                                      /* make it floor division */
+        q -= 1;
+        rem += g;
+    }
+    const int64_t half = g / 2;
+    if (rem > half || (rem == half && (q % 2 != 0)))
+        q += 1;
+    int64_t r = q * g;
+    if (r > INT32_MAX)
+        r = ((int64_t)INT32_MAX / g) * g;
+    return (int32_t)r;
+}
+
+static int32_t round_int_to_noise_1(int32_t x, double G2)
+{
+    if (!(G2 > 0.0) || isinf(G2))
+        return x;
+    return oracle_round_int_to_multiple(x, oracle_granularity_exponent(G2));
+}
+
+/* As oracle_round_to_noise for int32 visibilities [F][P][T][2] and int32
+ * autos [F][I][T].  The product V_ii V_jj is exact in int64 and is rounded
+ * once to double; G2 = that * c (crosses) or * 2c (autos). */
+int oracle_round_to_noise_i32(const int32_t *vis_in, int32_t *vis_out, const int32_t *autos,
+                              int64_t F, int64_t I, int64_t T, const int32_t *prod_map,
+                              double n_samples, double f, int nthreads)
+{
+    if (F < 0 || I < 0 || T < 0)
+        return -1;
+    if (!(n_samples > 0.0) || isinf(n_samples) || !(f >= 0.0) || isinf(f))
+        return -1;
+    const int64_t P = I * (I + 1) / 2;
+    if (F * P * T > 0 && (!vis_in || !vis_out || !autos))
+        return -1;
+    int32_t *pairs = (int32_t *)malloc((size_t)(P > 0 ? P : 1) * 2 * sizeof(int32_t));
+    if (!pairs)
+        return -1;
+    if (prod_map) {
+        for (int64_t p = 0; p < P; p++) {
+            if (prod_map[2 * p] < 0 || prod_map[2 * p] >= I || prod_map[2 * p + 1] < 0 ||
+                prod_map[2 * p + 1] >= I) {
+                free(pairs);
+                return -1;
+            }
+            pairs[2 * p] = prod_map[2 * p];
+            pairs[2 * p + 1] = prod_map[2 * p + 1];
+        }
+    } else {
+        int64_t p = 0;
+        for (int64_t i = 0; i < I; i++)
+            for (int64_t j = i; j < I; j++) {
+                pairs[2 * p] = (int32_t)i;
+                pairs[2 * p + 1] = (int32_t)j;
+                p++;
+            }
+    }
+    const double c = (12.0 * f) / (2.0 * n_samples);
+    const double c_auto = 2.0 * c;
+    const int64_t rows = F * P;
+#pragma omp parallel for num_threads(pick_threads(nthreads)) schedule(static)
+    for (int64_t row = 0; row < rows; row++) {
+        const int64_t fr = row / P, p = row % P;
+        const int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
+        const int32_t *Ai = autos + (fr * I + i) * T;
+        const int32_t *Aj = autos + (fr * I + j) * T;
+        for (int64_t t = 0; t < T; t++) {
+            const int64_t e = 2 * (row * T + t);
+            const int32_t re = vis_in[e], im = vis_in[e + 1];
+            if (i != j) {
+                const double G2 = (double)((int64_t)Ai[t] * (int64_t)Aj[t]) * c;
+                vis_out[e] = round_int_to_noise_1(re, G2);
+                vis_out[e + 1] = round_int_to_noise_1(im, G2);
+            } else {
+                const double G2 = (double)((int64_t)Ai[t] * (int64_t)Ai[t]) * c_auto;
+                vis_out[e] = round_int_to_noise_1(re, G2);
+                vis_out[e + 1] = im;
+            }
+        }
+    }
+    free(pairs);
+    return 0;
+}
+
 /* ======================================================================
  * Stage 2a: bit transpose within blocks (Section 4.2)
  * ====================================================================== */

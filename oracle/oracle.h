@@ -40,6 +40,16 @@ int oracle_granularity_exponent(double G2);
 /* Round one float to the nearest multiple of 2^k, ties to the even multiple. */
 float oracle_round_to_multiple(float x, int k);
 
+/* Integer visibilities (Section 5 data type): int32 [F][P][T][2] and int32
+ * autos [F][I][T]; G2 from the exact int64 product rounded once to double;
+ * rounding to a multiple of 2^k only for k >= 1, ties to even in integer
+ * arithmetic, a result above INT32_MAX saturating to the largest multiple
+ * that fits. */
+int32_t oracle_round_int_to_multiple(int32_t x, int k);
+int oracle_round_to_noise_i32(const int32_t *vis_in, int32_t *vis_out, const int32_t *autos,
+                              int64_t F, int64_t I, int64_t T, const int32_t *prod_map,
+                              double n_samples, double f, int nthreads);
+
 /* Section 4.2: bit transpose of each block of block_size elements (a multiple
  * of 8; 0 = 8192 bytes' worth); the last partial block keeps floor(rem/8)*8
  * elements and the final n mod 8 elements are copied verbatim. */

@@ -18,7 +18,7 @@ from ._lib import (BSG_ECAPACITY, BSG_ECORRUPT, BSG_EHIP, BSG_EINVAL, BSG_OK, Bs
                    Header)
 
 __all__ = [
-    "round_to_noise", "bitshuffle", "bitunshuffle", "compress_bound", "workspace_size",
+    "round_to_noise", "round_to_noise_i32", "bitshuffle", "bitunshuffle", "compress_bound", "workspace_size",
     "compress", "round_compress", "decompress", "block_elems", "read_header", "BsgError",
     "compress_sync", "decompress_sync", "BSG_OK", "BSG_EINVAL", "BSG_ECAPACITY",
     "BSG_ECORRUPT", "BSG_EHIP", "load", "BatchPlan",
@@ -77,6 +77,27 @@ def round_to_noise(vis: torch.Tensor, autos: torch.Tensor, n_samples: float, f: 
     _lib.check(_lib.lib().bsg_round_to_noise(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
                                               _ptr(prod_map), float(n_samples), float(f),
                                               _stream_ptr(stream)), "round_to_noise")
+    return out
+
+
+def round_to_noise_i32(vis: torch.Tensor, autos: torch.Tensor, n_samples: float, f: float,
+                       out: torch.Tensor | None = None, prod_map: torch.Tensor | None = None,
+                       stream=None) -> torch.Tensor:
+    """Integer visibilities: vis int32 (F, P, T, 2), autos int32 (F, I, T) ->
+    rounded vis (out may be vis itself)."""
+    _require_device(vis, autos, out, prod_map)
+    if vis.dtype != torch.int32 or autos.dtype != torch.int32:
+        raise TypeError("vis and autos must be int32")
+    F, I, T = autos.shape
+    if tuple(vis.shape) != (F, I * (I + 1) // 2, T, 2):
+        raise ValueError(f"vis {tuple(vis.shape)} does not match autos {tuple(autos.shape)}")
+    if out is None:
+        out = torch.empty_like(vis)
+    if prod_map is not None and (prod_map.dtype != torch.int32 or tuple(prod_map.shape) != (vis.shape[1], 2)):
+        raise ValueError("prod_map must be int32 (P, 2)")
+    _lib.check(_lib.lib().bsg_round_to_noise_i32(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
+                                                  _ptr(prod_map), float(n_samples), float(f),
+                                                  _stream_ptr(stream)), "round_to_noise_i32")
     return out
 
 

@@ -23,7 +23,7 @@ EXPORTS = (
     "bsg_bitunshuffle", "bsg_compress_bound", "bsg_compress_workspace_size",
     "bsg_compress_lz4", "bsg_round_compress_lz4", "bsg_decompress_lz4", "bsg_read_header",
     "bsg_batch_table_bytes", "bsg_batch_build_table", "bsg_batch_workspace_size",
-    "bsg_batch_compress", "bsg_batch_decompress",
+    "bsg_batch_compress", "bsg_batch_decompress", "bsg_round_to_noise_i32",
 )
 
 
@@ -65,6 +65,8 @@ def _lib():
         L.bsg_block_elems.restype = i64
         L.bsg_round_to_noise.argtypes = [vp, vp, vp, i64, i64, i64, vp, dbl, dbl, vp]
         L.bsg_round_to_noise.restype = i32
+        L.bsg_round_to_noise_i32.argtypes = [vp, vp, vp, i64, i64, i64, vp, dbl, dbl, vp]
+        L.bsg_round_to_noise_i32.restype = i32
         for f in (L.bsg_bitshuffle, L.bsg_bitunshuffle):
             f.argtypes = [vp, vp, i64, i64, i64, vp]
             f.restype = i32

@@ -53,6 +53,7 @@ inline RoundParams make_round(const float *autos, const int32_t *prod_map, int64
 {
     RoundParams rp;
     rp.autos = autos;
+    rp.autos_i32 = nullptr;
     rp.prod_map = prod_map;
     rp.F = F;
     rp.I = I;
@@ -102,6 +103,22 @@ int bsg_round_to_noise(const void *vis_in, void *vis_out, const float *autos, in
     const RoundParams rp = make_round(autos, prod_map, F, I, T, n_samples, f);
     return hip_status(launch_round(static_cast<const float *>(vis_in), static_cast<float *>(vis_out),
                                    rp, static_cast<hipStream_t>(stream)));
+}
+
+int bsg_round_to_noise_i32(const void *vis_in, void *vis_out, const int32_t *autos, int64_t F,
+                           int64_t I, int64_t T, const int32_t *prod_map, double n_samples,
+                           double f, void *stream)
+{
+    if (!round_args_ok(F, I, T, n_samples, f)) return BSG_EINVAL;
+    const int64_t P = I * (I + 1) / 2;
+    if (F * P * T == 0) return BSG_OK;
+    if (!vis_in || !vis_out || !autos) return BSG_EINVAL;
+    if ((uintptr_t)vis_in % 8 || (uintptr_t)vis_out % 8 || (uintptr_t)autos % 4) return BSG_EINVAL;
+    RoundParams rp = make_round(nullptr, prod_map, F, I, T, n_samples, f);
+    rp.autos_i32 = autos;
+    return hip_status(launch_round_i32(static_cast<const int32_t *>(vis_in),
+                                       static_cast<int32_t *>(vis_out), rp,
+                                       static_cast<hipStream_t>(stream)));
 }
 
 static int shuffle_common(const void *in, void *out, int64_t n, int64_t E, int64_t block_size,

@@ -60,30 +60,15 @@ __device__ __forceinline__ void stage_fast(const uint8_t *__restrict__ src, int6
         load_unit<E>(src + u * (Unit<E>::G * E), w);
         if constexpr (ROUND) {
             // E == 4: the unit is 32 float32 = 16 complex64 visibilities.
-            const int64_t ci0 = (first_elem + u * 32) / 2;
-            int64_t row = ci0 / rp.T;
-            int64_t t = ci0 - row * rp.T;
-            int64_t fr = row / rp.P;
-            int64_t p = row - fr * rp.P;
-            int32_t i, j;
-            product_pair(rp, p, i, j);
+            VisCursor c = cursor_at(rp, (first_elem + u * 32) / 2);
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                const float ai = rp.autos[(fr * rp.I + i) * rp.T + t];
-                const float aj = rp.autos[(fr * rp.I + j) * rp.T + t];
-                const float2 o = round_complex(make_float2(__uint_as_float(w[2 * k]),
-                                                           __uint_as_float(w[2 * k + 1])),
-                                               ai, aj, i == j, rp);
+                const float2 o = round_at(make_float2(__uint_as_float(w[2 * k]),
+                                                      __uint_as_float(w[2 * k + 1])),
+                                          c, rp);
                 w[2 * k] = __float_as_uint(o.x);
                 w[2 * k + 1] = __float_as_uint(o.y);
-                if (++t == rp.T) {
-                    t = 0;
-                    if (++p == rp.P) {
-                        p = 0;
-                        ++fr;
-                    }
-                    product_pair(rp, p, i, j);
-                }
+                if (k < 15) cursor_advance(rp, c, 1);
             }
         }
         unit_forward<E>(w);

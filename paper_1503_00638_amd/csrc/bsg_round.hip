@@ -18,11 +18,12 @@ namespace bsg {
 
 namespace {
 
-constexpr int kComplexPerThread = 4;
+constexpr int kComplexPerThread = 8;
 
-// A wavefront rounds 256 consecutive visibilities; lane l takes elements
-// l, l + 64, l + 128, l + 192 of them, so every load and store instruction
-// of the wave touches 512 contiguous bytes.
+// A wavefront rounds 512 consecutive visibilities; lane l takes elements
+// l, l + 64, ..., l + 448 of them, so every load and store instruction of the
+// wave touches 512 contiguous bytes.  The position (time, product, inputs,
+// auto rows) is found once per lane and then stepped.
 __global__ __launch_bounds__(256) void k_round(const float2 *__restrict__ vin,
                                                float2 *__restrict__ vout, RoundParams rp,
                                                int64_t n_complex)
@@ -31,30 +32,30 @@ __global__ __launch_bounds__(256) void k_round(const float2 *__restrict__ vin,
     const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     int64_t e = wave * (kWave * kComplexPerThread) + lane;
     if (e >= n_complex) return;
-    int64_t row = e / rp.T;
-    int64_t t = e - row * rp.T;
-    int64_t fr = row / rp.P;
-    int64_t p = row - fr * rp.P;
-    int32_t i, j;
-    product_pair(rp, p, i, j);
-    for (int k = 0; k < kComplexPerThread && e < n_complex; ++k) {
-        const float2 v = vin[e];
-        const float ai = rp.autos[(fr * rp.I + i) * rp.T + t];
-        const float aj = rp.autos[(fr * rp.I + j) * rp.T + t];
-        vout[e] = round_complex(v, ai, aj, i == j, rp);
-        // advance by one wave width (64 visibilities)
+    VisCursor c = cursor_at(rp, e);
+    for (int k = 0;;) {
+        vout[e] = round_at(vin[e], c, rp);
         e += kWave;
-        t += kWave;
-        if (t >= rp.T) {
-            while (t >= rp.T) {
-                t -= rp.T;
-                if (++p == rp.P) {
-                    p = 0;
-                    ++fr;
-                }
-            }
-            product_pair(rp, p, i, j);
-        }
+        if (++k == kComplexPerThread || e >= n_complex) break;
+        cursor_advance(rp, c, kWave);
+    }
+}
+
+// The same walk over integer visibilities (int32 re, im).
+__global__ __launch_bounds__(256) void k_round_i32(const int2 *__restrict__ vin,
+                                                   int2 *__restrict__ vout, RoundParams rp,
+                                                   int64_t n_complex)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    int64_t e = wave * (kWave * kComplexPerThread) + lane;
+    if (e >= n_complex) return;
+    VisCursor c = cursor_at(rp, e);
+    for (int k = 0;;) {
+        vout[e] = round_at_i32(vin[e], c, rp);
+        e += kWave;
+        if (++k == kComplexPerThread || e >= n_complex) break;
+        cursor_advance(rp, c, kWave);
     }
 }
 
@@ -69,6 +70,18 @@ hipError_t launch_round(const float *vin, float *vout, const RoundParams &rp, hi
     hipLaunchKernelGGL(k_round, dim3((unsigned)blocks), dim3(256), 0, s,
                        reinterpret_cast<const float2 *>(vin), reinterpret_cast<float2 *>(vout),
                        rp, n_complex);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_i32(const int32_t *vin, int32_t *vout, const RoundParams &rp, hipStream_t s)
+{
+    const int64_t n_complex = rp.F * rp.P * rp.T;
+    if (n_complex == 0) return hipSuccess;
+    const int64_t waves = (n_complex + kWave * kComplexPerThread - 1) / (kWave * kComplexPerThread);
+    const int64_t blocks = (waves * kWave + 255) / 256;
+    hipLaunchKernelGGL(k_round_i32, dim3((unsigned)blocks), dim3(256), 0, s,
+                       reinterpret_cast<const int2 *>(vin), reinterpret_cast<int2 *>(vout), rp,
+                       n_complex);
     return hipGetLastError();
 }
 

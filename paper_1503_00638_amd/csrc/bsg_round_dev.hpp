@@ -27,48 +27,28 @@ __device__ __forceinline__ void product_pair(const RoundParams &rp, int64_t p, i
     j = (int32_t)(rp.I - 1 - in_row);
 }
 
-// Largest integer k with 4^k < G2, for G2 > 0 and finite, from the bits of
-// G2 = m 2^E (1 <= m < 2): k = floor(E/2) when m > 1, floor((E-1)/2) when
-// G2 is an exact power of two.
+// Largest integer k with 4^k < G2, for G2 > 0 and finite.  With G2 = m 2^e,
+// 1/2 <= m < 1 (frexp, subnormals included): k = floor((e - 1) / 2), or
+// floor((e - 2) / 2) when G2 is an exact power of two (4^k = G2 must not
+// count).
 __device__ __forceinline__ int granularity_k(double G2)
 {
-    const uint64_t u = (uint64_t)__double_as_longlong(G2);
-    const int ex = (int)(u >> 52);
-    uint64_t mant = u & 0xFFFFFFFFFFFFFull;
-    int E;
-    if (ex == 0) { // subnormal double: value = mant * 2^-1074
-        const int top = 63 - __clzll((long long)mant);
-        E = top - 1074;
-        mant &= ~(1ull << top);
-    } else {
-        E = ex - 1023;
-    }
-    return mant == 0 ? ((E - 1) >> 1) : (E >> 1); // >> on int is floor division
+    const int e = __builtin_amdgcn_frexp_exp(G2);
+    const double m = __builtin_amdgcn_frexp_mant(G2);
+    return (m == 0.5 ? e - 2 : e - 1) >> 1; // >> on int is floor division
 }
 
-// Round float32 bits x to the nearest multiple of 2^k, ties to even, keeping
-// the sign (a result of zero keeps the sign of x); NaN and Inf unchanged.
-// With ulp(x) = 2^(max(exp,1) - 150), d = k - log2 ulp low magnitude bits
-// are cleared after adding the round-half-even increment; a carry into the
-// exponent field is the correct next binade (and 0x7f800000 = Inf on
-// overflow).
+// Round float32 bits x to the nearest multiple of 2^k, ties to even: in
+// double, x 2^-k and back are exact scalings (|k| stays far below the double
+// exponent range for any finite float G2), rint rounds half to even and
+// keeps the sign of zero, and the result is a float (a multiple of 2^k no
+// larger than |x| + 2^k/2, or Inf past the float range).  NaN and Inf are
+// returned as they are.
 __device__ __forceinline__ uint32_t round_bits(uint32_t x, int k)
 {
-    const uint32_t mag = x & 0x7FFFFFFFu;
-    const int ex = (int)(mag >> 23);
-    if (ex == 255) return x;
-    const int d = k - ((ex == 0 ? 1 : ex) - 150);
-    if (d <= 0) return x;
-    const uint32_t sign = x & 0x80000000u;
-    if (d >= 25 || (d == 24 && ex == 0)) return sign; // |x| < g/2
-    if (d == 24) // g/2 <= |x| < g: the tie g/2 goes to 0 (even), else to g
-        return sign | (((mag & 0x7FFFFFu) == 0) ? 0u : ((uint32_t)(ex + 1) << 23));
-    // parity of floor(|x| / g): bit d of the significand (1.m or 0.m); for
-    // a normal x with d == 23 that is the implicit leading 1, not bit 23 of
-    // the stored magnitude (the exponent's lowest bit)
-    const uint32_t odd = (d == 23 && ex != 0) ? 1u : ((mag >> d) & 1u);
-    const uint32_t inc = (1u << (d - 1)) - 1u + odd;
-    return sign | ((mag + inc) & ~((1u << d) - 1u));
+    if ((x & 0x7F800000u) == 0x7F800000u) return x;
+    const double y = __builtin_ldexp((double)__uint_as_float(x), -k);
+    return __float_as_uint((float)__builtin_ldexp(__builtin_rint(y), k));
 }
 
 __device__ __forceinline__ uint32_t round_noise_bits(uint32_t x, double G2)
@@ -77,35 +57,132 @@ __device__ __forceinline__ uint32_t round_noise_bits(uint32_t x, double G2)
     return round_bits(x, granularity_k(G2));
 }
 
-// One complex visibility.  ai = V_ii, aj = V_jj at the same (f, t).
+// One complex visibility.  ai = V_ii, aj = V_jj at the same (f, t).  Both
+// components of a cross product share one G2 and one k.
 __device__ __forceinline__ float2 round_complex(float2 v, float ai, float aj, bool is_auto,
                                                 const RoundParams &rp)
 {
+    const double G2 = ((double)ai * (double)aj) * (is_auto ? rp.c_auto : rp.c);
+    if (!(G2 > 0.0) || G2 == __builtin_inf()) return v;
+    const int k = granularity_k(G2);
     float2 o;
-    if (!is_auto) {
-        const double G2 = ((double)ai * (double)aj) * rp.c;
-        o.x = __uint_as_float(round_noise_bits(__float_as_uint(v.x), G2));
-        o.y = __uint_as_float(round_noise_bits(__float_as_uint(v.y), G2));
-    } else {
-        const double G2 = ((double)ai * (double)ai) * rp.c_auto;
-        o.x = __uint_as_float(round_noise_bits(__float_as_uint(v.x), G2));
-        o.y = v.y;
-    }
+    o.x = __uint_as_float(round_bits(__float_as_uint(v.x), k));
+    o.y = is_auto ? v.y : __uint_as_float(round_bits(__float_as_uint(v.y), k));
     return o;
+}
+
+// a / b and a % b for non-negative a, b > 0: 32-bit division when both fit.
+__device__ __forceinline__ void divmod(int64_t a, int64_t b, int64_t &q, int64_t &r)
+{
+    if (((uint64_t)a | (uint64_t)b) >> 32 == 0) {
+        const uint32_t q32 = (uint32_t)a / (uint32_t)b;
+        q = q32;
+        r = (int64_t)((uint32_t)a - q32 * (uint32_t)b);
+    } else {
+        q = a / b;
+        r = a - q * b;
+    }
+}
+
+// Position of a visibility in the [F][P][T] array with its product's inputs
+// and the offsets of its two auto-correlation rows in [F][I][T]; stepping
+// through time and products needs no division.
+struct VisCursor {
+    int64_t t, p, fr;
+    int32_t i, j;
+    int64_t row_i, row_j; // (fr I + i) T and (fr I + j) T
+};
+
+__device__ __forceinline__ void cursor_rows(const RoundParams &rp, VisCursor &c)
+{
+    c.row_i = (c.fr * rp.I + c.i) * rp.T;
+    c.row_j = (c.fr * rp.I + c.j) * rp.T;
+}
+
+__device__ __forceinline__ VisCursor cursor_at(const RoundParams &rp, int64_t ci)
+{
+    VisCursor c;
+    int64_t row;
+    divmod(ci, rp.T, row, c.t);
+    divmod(row, rp.P, c.fr, c.p);
+    product_pair(rp, c.p, c.i, c.j);
+    cursor_rows(rp, c);
+    return c;
+}
+
+// The next product (upper-triangle order steps j, then i; past the last
+// product the next frequency).
+__device__ __forceinline__ void cursor_next_product(const RoundParams &rp, VisCursor &c)
+{
+    if (++c.p == rp.P) {
+        c.p = 0;
+        ++c.fr;
+    }
+    if (rp.prod_map) {
+        c.i = rp.prod_map[2 * c.p];
+        c.j = rp.prod_map[2 * c.p + 1];
+    } else if (c.p == 0) {
+        c.i = c.j = 0;
+    } else if (++c.j == rp.I) {
+        c.j = ++c.i;
+    }
+    cursor_rows(rp, c);
+}
+
+__device__ __forceinline__ void cursor_advance(const RoundParams &rp, VisCursor &c, int64_t dt)
+{
+    c.t += dt;
+    while (c.t >= rp.T) {
+        c.t -= rp.T;
+        cursor_next_product(rp, c);
+    }
+}
+
+__device__ __forceinline__ float2 round_at(float2 v, const VisCursor &c, const RoundParams &rp)
+{
+    const float ai = rp.autos[c.row_i + c.t];
+    const float aj = rp.autos[c.row_j + c.t];
+    return round_complex(v, ai, aj, c.i == c.j, rp);
+}
+
+// Integer visibilities: the nearest multiple of 2^k, ties to the even
+// multiple, in exact integer arithmetic; only k >= 1 changes an integer.  A
+// result above INT32_MAX becomes the largest multiple of 2^k that fits (the
+// negative side always fits: -2^31 is a multiple of every 2^k, k <= 31).
+__device__ __forceinline__ int32_t round_int(int32_t x, int k)
+{
+    if (k <= 0) return x;
+    if (k > 62) k = 62; // |x| <= 2^31 < g/2
+    const int64_t g = (int64_t)1 << k;
+    int64_t q = (int64_t)x >> k; // floor division
+    const int64_t rem = (int64_t)x - q * g;
+    if (rem > (g >> 1) || (rem == (g >> 1) && (q & 1))) ++q;
+    int64_t r = q * g;
+    if (r > 2147483647ll) r = (2147483647ll >> k) * g;
+    return (int32_t)r;
+}
+
+// One integer visibility (re, im); G2 from the exact int64 product of the
+// two autos rounded once to double.
+__device__ __forceinline__ int2 round_at_i32(int2 v, const VisCursor &c, const RoundParams &rp)
+{
+    const int64_t ai = rp.autos_i32[c.row_i + c.t];
+    const int64_t aj = rp.autos_i32[c.row_j + c.t];
+    const bool is_auto = c.i == c.j;
+    const double G2 = (double)(ai * aj) * (is_auto ? rp.c_auto : rp.c);
+    if (!(G2 > 0.0) || G2 == __builtin_inf()) return v;
+    const int k = granularity_k(G2);
+    return make_int2(round_int(v.x, k), is_auto ? v.y : round_int(v.y, k));
 }
 
 // Element e of the visibility array viewed as float32 (component e & 1 of
 // visibility e >> 1), rounded.  Used where elements are visited one by one.
 __device__ __forceinline__ uint32_t round_element(uint32_t x, int64_t e, const RoundParams &rp)
 {
-    const int64_t ci = e >> 1;
-    const int64_t row = ci / rp.T, t = ci - row * rp.T;
-    const int64_t fr = row / rp.P, p = row - fr * rp.P;
-    int32_t i, j;
-    product_pair(rp, p, i, j);
-    const float ai = rp.autos[(fr * rp.I + i) * rp.T + t];
-    const float aj = rp.autos[(fr * rp.I + j) * rp.T + t];
-    if (i != j) return round_noise_bits(x, ((double)ai * (double)aj) * rp.c);
+    const VisCursor c = cursor_at(rp, e >> 1);
+    const float ai = rp.autos[c.row_i + c.t];
+    const float aj = rp.autos[c.row_j + c.t];
+    if (c.i != c.j) return round_noise_bits(x, ((double)ai * (double)aj) * rp.c);
     if ((e & 1) == 0) return round_noise_bits(x, ((double)ai * (double)ai) * rp.c_auto);
     return x;
 }

@@ -92,6 +92,21 @@ def gen_vis(F: int, I: int, T: int, seed: int, n_samples: float = N_SAMPLES_DEFA
     return vis, autos
 
 
+def gen_vis_int(F: int, I: int, T: int, seed: int, n_samples: float = N_SAMPLES_DEFAULT,
+                scale: float = 1024.0):
+    """Integer visibilities, the data type of the paper's correlator output:
+    the model above scaled by `scale` and rounded to integers.  Returns
+    (vis int32 (F, P, T, 2), autos int32 (F, I, T)), autos being the real
+    parts of the auto products."""
+    vis, _ = gen_vis(F, I, T, seed, n_samples)
+    vi = np.rint(vis.view(np.float32).reshape(F, -1, T, 2).astype(np.float64) * scale)
+    vi = vi.astype(np.int32)
+    pairs = product_pairs(I)
+    is_auto = pairs[:, 0] == pairs[:, 1]
+    autos = np.ascontiguousarray(vi[..., 0][:, is_auto, :])
+    return vi, autos
+
+
 # ---------------------------------------------------------------------------
 # bit-transpose sweep inputs
 # ---------------------------------------------------------------------------

@@ -1,0 +1,85 @@
+"""GPU parity for integer visibilities (the correlator's own data type,
+Section 5): int32 rounding equals the oracle bit for bit, and the rounded
+values compress (elem_size 8: one complex value per element) to the
+oracle's stream."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_00638_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = synth.N_SAMPLES_DEFAULT
+I32 = np.iinfo(np.int32)
+
+
+@pytest.fixture(scope="module")
+def bsg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1503_00638_amd as m
+    m.load()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("F,I,T,seed,f,scale", [(16, 8, 64, 0, 0.01, 1024.0), (3, 5, 7, 1, 0.01, 4096.0),
+                                                (1, 1, 1, 2, 0.1, 1e5), (2, 16, 33, 3, 1e-3, 1024.0),
+                                                (4, 12, 5, 4, 1e-5, 1e6), (2, 3, 9, 5, 0.0, 1024.0),
+                                                (2, 4, 40, 6, 0.01, 1.0)])
+def test_round_i32_parity(bsg, F, I, T, seed, f, scale):
+    vis, autos = synth.gen_vis_int(F, I, T, seed, scale=scale)
+    ref = oracle.round_to_noise_i32(vis, autos, N, f)
+    got = host(bsg.round_to_noise_i32(dev(vis), dev(autos), N, f))
+    assert np.array_equal(got, ref)
+
+
+def test_round_i32_extremes(bsg):
+    rng = np.random.default_rng(7)
+    F, I, T = 3, 6, 40
+    vis, autos = synth.gen_vis_int(F, I, T, 7, scale=1024.0)
+    flat = vis.reshape(-1)
+    flat[::3] = rng.integers(I32.min, I32.max, flat[::3].size, endpoint=True, dtype=np.int64)
+    flat[1::7] = I32.max
+    flat[2::11] = I32.min
+    flat[5::13] = 0
+    # autos spanning g from 1 to beyond 2^31, zero, negative and mixed-sign
+    autos[0] = rng.integers(-10**6, 2**31 - 1, autos[0].size).reshape(autos[0].shape)
+    autos[1, 0, :4] = [0, -5, -(2**31), 2**31 - 1]
+    autos[2] = 2**31 - 1
+    for f in (0.01, 1.0, 1e-5):
+        ref = oracle.round_to_noise_i32(vis, autos, N, f)
+        got = host(bsg.round_to_noise_i32(dev(vis), dev(autos), N, f))
+        assert np.array_equal(got, ref), f
+
+
+def test_round_i32_prod_map_and_in_place(bsg):
+    vis, autos = synth.gen_vis_int(3, 5, 16, 8, scale=2048.0)
+    P = vis.shape[1]
+    pm = np.ascontiguousarray(synth.product_pairs(5)[np.random.default_rng(1).permutation(P)])
+    ref = oracle.round_to_noise_i32(vis, autos, N, 0.01, prod_map=pm)
+    dv = dev(vis)
+    bsg.round_to_noise_i32(dv, dev(autos), N, 0.01, out=dv, prod_map=dev(pm))
+    assert np.array_equal(host(dv), ref)
+
+
+@pytest.mark.parametrize("F,I,T,B", [(16, 8, 64, 1024), (3, 5, 7, 128), (8, 16, 32, 0), (2, 3, 5, 8)])
+def test_int_pipeline_stream(bsg, F, I, T, B):
+    vis, autos = synth.gen_vis_int(F, I, T, F + I + T, scale=1024.0)
+    r = oracle.round_to_noise_i32(vis, autos, N, 0.01)
+    ref = oracle.compress(r.view(np.uint8).reshape(-1), 8, B)
+    dr = bsg.round_to_noise_i32(dev(vis), dev(autos), N, 0.01)
+    s = host(bsg.compress_sync(dr.view(torch.uint8).reshape(-1), 8, B))
+    assert np.array_equal(s, ref)
+    back = host(bsg.decompress_sync(dev(ref), r.size // 2, 8, B))
+    assert np.array_equal(back, r.view(np.uint8).reshape(-1))
