@@ -330,8 +330,10 @@ __device__ __forceinline__ bool read_len_ext(const uint8_t *ci, int &ip, int ien
 {
     const int lane = threadIdx.x;
     for (;;) {
+        // every lane reads (clamped into the input), so no lane branches
         const int pos = ip + lane;
-        const uint32_t v = pos < iend ? ci[pos] : 0u;
+        const uint32_t byte = ci[pos < iend ? pos : iend - 1];
+        const uint32_t v = pos < iend ? byte : 0u;
         const uint64_t m = __ballot(v != 255u);
         if (m == 0) {
             len += 255 * kWave;
@@ -340,7 +342,7 @@ __device__ __forceinline__ bool read_len_ext(const uint8_t *ci, int &ip, int ien
         }
         const int f = __builtin_ctzll(m);
         if (ip + f >= iend) return false;
-        len += 255 * f + __shfl((int)v, f);
+        len = __builtin_amdgcn_readfirstlane(len + 255 * f + __shfl((int)v, f));
         ip += f + 1;
         return true;
     }
@@ -454,6 +456,10 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 
 __device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend, int ob)
 {
+    // A length that fails every check below: a length field whose
+    // continuation runs past the input is reported through it, so each
+    // sequence has only three exits (bad literals, end of block, bad match).
+    constexpr int kBadLength = 1 << 30;
     uint8_t *b8 = reinterpret_cast<uint8_t *>(b32);
     int ip = uni(ip0), op = 0;
     iend = uni(iend);
@@ -463,54 +469,57 @@ __device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend,
         ip = uni(ip);
         op = uni(op);
         w = (uint32_t)uni((int)w);
-        if (ip >= iend) return false;
         const uint32_t tok = w & 255u;
         int ll = (int)(tok >> 4);
         int lit = ip + 1;
         if (ll == 15) {
             const int e = (int)((w >> 8) & 255u);
-            if (ip + 1 >= iend) return false;
             if (e != 255) {
                 ll += e;
                 lit = ip + 2;
             } else {
                 int q = ip + 1;
-                const int okl = uni(read_len_ext(b8, q, iend, ll) ? 1 : 0);
-                if (!okl) return false;
+                if (!read_len_ext(b8, q, iend, ll)) ll = kBadLength;
                 lit = uni(q);
                 ll = uni(ll);
             }
         }
         ll = uni(ll);
         lit = uni(lit);
-        if (ll > iend - lit || ll > ob - op || op > lit) return false;
+        // token, length bytes and literals inside the input (lit + ll <= iend
+        // also puts the length bytes before iend); output inside the block and
+        // never past unread input
+        // (all quantities are far below 2^31: a check fails iff its difference
+        // is negative, so one sign test covers them all)
+        if (((iend - 1 - ip) | (iend - lit - ll) | (ob - op - ll) | (lit - op)) < 0) return false;
         const int ip2 = lit + ll;
         uint32_t ow = lds_le32(b32, ip2); // offset and first length byte
         dcopy(b32, op, lit, ll);
         op += ll;
         if (ip2 == iend) break;
         ow = __builtin_amdgcn_readfirstlane(ow);
-        if (iend - ip2 < 2) return false;
         const int off = (int)(ow & 0xFFFFu);
         int ml = (int)(tok & 15u) + kMinMatch;
         int nip = ip2 + 2;
         if ((tok & 15u) == 15u) {
-            if (nip >= iend) return false;
             const int e = (int)((ow >> 16) & 255u);
             if (e != 255) {
                 ml += e;
                 nip = ip2 + 3;
             } else {
                 int q = ip2 + 2;
-                const int okm = uni(read_len_ext(b8, q, iend, ml) ? 1 : 0);
-                if (!okm) return false;
+                if (!read_len_ext(b8, q, iend, ml)) ml = kBadLength;
                 nip = uni(q);
                 ml = uni(ml);
             }
         }
         ml = uni(ml);
         nip = uni(nip);
-        if (off == 0 || off > op || ml > ob - op || op + ml > nip) return false;
+        // offset and length bytes inside the input with a token after them
+        // (nip < iend), offset into the output so far, output inside the
+        // block and never past unread input
+        if (((iend - 1 - nip) | (off - 1) | (op - off) | (ob - op - ml) | (nip - op - ml)) < 0)
+            return false;
         w = lds_le32(b32, nip); // next token, read together with the match source
         dmatch(b32, op, off, ml);
         w = __builtin_amdgcn_readfirstlane(w);
