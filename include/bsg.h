@@ -89,6 +89,28 @@ int bsg_round_to_noise(const void *vis_in, void *vis_out, const float *autos, in
                        int64_t I, int64_t T, const int32_t *prod_map, double n_samples,
                        double f, void *stream);
 
+/* Compensation of the diagonal noise model (Section 3.2): the diagonal
+ * radiometer equation ignores how correlated the products are; multiplying
+ * f by the minimum over cross products of 1 - |V_ij|^2 / (V_ii V_jj) makes
+ * up for it, here per frequency and time.
+ * vis: complex64 [F][P][T]; autos: float32 [F][I][T] (as bsg_round_to_noise).
+ * scale: device float64 [F][T], 8-byte aligned, receives per (f, t) the
+ *   minimum over products with i != j of 1 - (re^2 + im^2) / (V_ii V_jj),
+ *   each term in double in that order; products with V_ii V_jj not positive
+ *   and finite, and NaN terms, are skipped; 1 when no product is left.
+ * Errors: BSG_EINVAL (negative sizes, NULL or misaligned pointers, more
+ *   than 2^32 - 1 frequencies); BSG_EHIP. */
+int bsg_noise_compensation(const void *vis, const float *autos, int64_t F, int64_t I, int64_t T,
+                           const int32_t *prod_map, double *scale, void *stream);
+
+/* bsg_round_to_noise with a per-(f, t) factor on G2: G2 = ((V_ii V_jj) c)
+ * scale[f][t] for crosses and ((V_ii V_ii) 2c) scale[f][t] for autos (scale
+ * from bsg_noise_compensation, or any factor on f; scale = 1 gives exactly
+ * bsg_round_to_noise).  scale: device float64 [F][T], 8-byte aligned. */
+int bsg_round_to_noise_scaled(const void *vis_in, void *vis_out, const float *autos, int64_t F,
+                              int64_t I, int64_t T, const int32_t *prod_map, double n_samples,
+                              double f, const double *scale, void *stream);
+
 /* Integer visibilities, the correlator's own data type (Section 5): the
  * same noise-relative rounding on int32 values.
  * vis_in / vis_out: int32 [F][P][T][2] (re, im), 8-byte aligned; may alias.

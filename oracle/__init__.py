@@ -52,6 +52,10 @@ def lib():
         L.oracle_round_int_to_multiple.restype = ctypes.c_int32
         L.oracle_round_to_noise_i32.argtypes = [vp, vp, vp, i64, i64, i64, vp, dbl, dbl, i32]
         L.oracle_round_to_noise_i32.restype = i32
+        L.oracle_noise_compensation.argtypes = [vp, vp, i64, i64, i64, vp, vp]
+        L.oracle_noise_compensation.restype = i32
+        L.oracle_round_to_noise_scaled.argtypes = [vp, vp, vp, i64, i64, i64, vp, dbl, dbl, vp, i32]
+        L.oracle_round_to_noise_scaled.restype = i32
         for name in ("oracle_bitshuffle", "oracle_bitunshuffle"):
             getattr(L, name).argtypes = [vp, vp, i64, i64, i64, i32]
             getattr(L, name).restype = i32
@@ -114,6 +118,40 @@ def round_to_noise(vis: np.ndarray, autos: np.ndarray, n_samples: float, f: floa
                                      float(n_samples), float(f), int(nthreads))
     if rc != 0:
         raise OracleError(rc, "round_to_noise")
+    return out
+
+
+def noise_compensation(vis: np.ndarray, autos: np.ndarray,
+                       prod_map: np.ndarray | None = None) -> np.ndarray:
+    """Per-(frequency, time) compensation factor (F, T) float64."""
+    vis = np.ascontiguousarray(vis, dtype=np.complex64)
+    autos = np.ascontiguousarray(autos, dtype=np.float32)
+    F, I, T = autos.shape
+    if vis.shape != (F, I * (I + 1) // 2, T):
+        raise ValueError(f"vis shape {vis.shape} does not match autos {autos.shape}")
+    out = np.empty((F, T), dtype=np.float64)
+    pm = None if prod_map is None else np.ascontiguousarray(prod_map, dtype=np.int32)
+    rc = lib().oracle_noise_compensation(_ptr(vis), _ptr(autos), F, I, T, _ptr(pm), _ptr(out))
+    if rc != 0:
+        raise OracleError(rc, "noise_compensation")
+    return out
+
+
+def round_to_noise_scaled(vis: np.ndarray, autos: np.ndarray, n_samples: float, f: float,
+                          scale: np.ndarray, prod_map: np.ndarray | None = None,
+                          nthreads: int = 0) -> np.ndarray:
+    vis = np.ascontiguousarray(vis, dtype=np.complex64)
+    autos = np.ascontiguousarray(autos, dtype=np.float32)
+    F, I, T = autos.shape
+    scale = np.ascontiguousarray(scale, dtype=np.float64)
+    if vis.shape != (F, I * (I + 1) // 2, T) or scale.shape != (F, T):
+        raise ValueError("shape mismatch")
+    out = np.empty_like(vis)
+    pm = None if prod_map is None else np.ascontiguousarray(prod_map, dtype=np.int32)
+    rc = lib().oracle_round_to_noise_scaled(_ptr(vis), _ptr(out), _ptr(autos), F, I, T, _ptr(pm),
+                                            float(n_samples), float(f), _ptr(scale), int(nthreads))
+    if rc != 0:
+        raise OracleError(rc, "round_to_noise_scaled")
     return out
 
 

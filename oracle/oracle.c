@@ -148,6 +148,122 @@ int oracle_round_to_noise(const float *vis_in, float *vis_out, const float *auto
 }
 
 /* ----------------------------------------------------------------------
+ * Compensation of the diagonal noise model (Section 3.2): the diagonal
+ * radiometer equation neglects the correlation between products; multiplying
+ * f by the minimum over cross products of 1 - |V_ij|^2 / (V_ii V_jj) roughly
+ * makes up for it.  The paper suggests doing so per frequency and time; here
+ * scale[f][t] is that minimum (1 when no cross product has V_ii V_jj > 0).
+ * ---------------------------------------------------------------------- */
+static int make_pairs(int64_t I, const int32_t *prod_map, int32_t **out)
+{
+    const int64_t P = I * (I + 1) / 2;
+    int32_t *pairs = (int32_t *)malloc((size_t)(P > 0 ? P : 1) * 2 * sizeof(int32_t));
+    if (!pairs)
+        return -1;
+    if (prod_map) {
+        for (int64_t p = 0; p < P; p++) {
+            if (prod_map[2 * p] < 0 || prod_map[2 * p] >= I || prod_map[2 * p + 1] < 0 ||
+                prod_map[2 * p + 1] >= I) {
+                free(pairs);
+                return -1;
+            }
+            pairs[2 * p] = prod_map[2 * p];
+            pairs[2 * p + 1] = prod_map[2 * p + 1];
+        }
+    } else {
+        int64_t p = 0;
+        for (int64_t i = 0; i < I; i++)
+            for (int64_t j = i; j < I; j++) {
+                pairs[2 * p] = (int32_t)i;
+                pairs[2 * p + 1] = (int32_t)j;
+                p++;
+            }
+    }
+    *out = pairs;
+    return 0;
+}
+
+int oracle_noise_compensation(const float *vis, const float *autos, int64_t F, int64_t I,
+                              int64_t T, const int32_t *prod_map, double *scale)
+{
+    if (F < 0 || I < 0 || T < 0)
+        return -1;
+    const int64_t P = I * (I + 1) / 2;
+    if (F * T > 0 && !scale)
+        return -1;
+    if (F * P * T > 0 && (!vis || !autos))
+        return -1;
+    int32_t *pairs;
+    if (make_pairs(I, prod_map, &pairs))
+        return -1;
+    for (int64_t fr = 0; fr < F; fr++)
+        for (int64_t t = 0; t < T; t++) {
+            double m = 1.0;
+            for (int64_t p = 0; p < P; p++) {
+                const int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
+                if (i == j)
+                    continue;
+                const double a = autos[(fr * I + i) * T + t], b = autos[(fr * I + j) * T + t];
+                const double ab = a * b;
+                if (!(ab > 0.0) || isinf(ab))
+                    continue;
+                const int64_t e = 2 * ((fr * P + p) * T + t);
+                const double re = vis[e], im = vis[e + 1];
+                const double term = 1.0 - (re * re + im * im) / ab;
+                if (term < m) /* a NaN term never wins */
+                    m = term;
+            }
+            scale[fr * T + t] = m;
+        }
+    free(pairs);
+    return 0;
+}
+
+/* oracle_round_to_noise with G2 multiplied by scale[f][t] (the compensation
+ * factor, or any per-sample factor on f): G2 = ((V_ii V_jj) c) scale for
+ * crosses and ((V_ii V_ii) 2c) scale for autos. */
+int oracle_round_to_noise_scaled(const float *vis_in, float *vis_out, const float *autos,
+                                 int64_t F, int64_t I, int64_t T, const int32_t *prod_map,
+                                 double n_samples, double f, const double *scale, int nthreads)
+{
+    if (F < 0 || I < 0 || T < 0)
+        return -1;
+    if (!(n_samples > 0.0) || isinf(n_samples) || !(f >= 0.0) || isinf(f))
+        return -1;
+    const int64_t P = I * (I + 1) / 2;
+    if (F * P * T > 0 && (!vis_in || !vis_out || !autos || !scale))
+        return -1;
+    int32_t *pairs;
+    if (make_pairs(I, prod_map, &pairs))
+        return -1;
+    const double c = (12.0 * f) / (2.0 * n_samples);
+    const double c_auto = 2.0 * c;
+    const int64_t rows = F * P;
+#pragma omp parallel for num_threads(pick_threads(nthreads)) schedule(static)
+    for (int64_t row = 0; row < rows; row++) {
+        const int64_t fr = row / P, p = row % P;
+        const int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
+        const float *Ai = autos + (fr * I + i) * T;
+        const float *Aj = autos + (fr * I + j) * T;
+        for (int64_t t = 0; t < T; t++) {
+            const int64_t e = 2 * (row * T + t);
+            const double sc = scale[fr * T + t];
+            if (i != j) {
+                const double G2 = (((double)Ai[t] * (double)Aj[t]) * c) * sc;
+                vis_out[e] = round_to_noise_1(vis_in[e], G2);
+                vis_out[e + 1] = round_to_noise_1(vis_in[e + 1], G2);
+            } else {
+                const double G2 = (((double)Ai[t] * (double)Ai[t]) * c_auto) * sc;
+                vis_out[e] = round_to_noise_1(vis_in[e], G2);
+                vis_out[e + 1] = vis_in[e + 1];
+            }
+        }
+    }
+    free(pairs);
+    return 0;
+}
+
+/* ----------------------------------------------------------------------
  * Integer visibilities (the data type of the paper's own evaluation,
  * Section 5): re and im are int32.  Every integer is already a multiple of
  * g = 1, so only k >= 1 changes anything (g <= 1 means no rounding).

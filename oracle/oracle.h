@@ -40,6 +40,17 @@ int oracle_granularity_exponent(double G2);
 /* Round one float to the nearest multiple of 2^k, ties to the even multiple. */
 float oracle_round_to_multiple(float x, int k);
 
+/* Section 3.2, compensation of the diagonal noise model: scale[F][T]
+ * (double) = per (frequency, time) the minimum over cross products of
+ * 1 - |V_ij|^2 / (V_ii V_jj), computed in double in that order; products
+ * with V_ii V_jj not positive and finite are skipped; 1 when none is left. */
+int oracle_noise_compensation(const float *vis, const float *autos, int64_t F, int64_t I,
+                              int64_t T, const int32_t *prod_map, double *scale);
+/* oracle_round_to_noise with G2 multiplied by scale[f][t] last. */
+int oracle_round_to_noise_scaled(const float *vis_in, float *vis_out, const float *autos,
+                                 int64_t F, int64_t I, int64_t T, const int32_t *prod_map,
+                                 double n_samples, double f, const double *scale, int nthreads);
+
 /* Integer visibilities (Section 5 data type): int32 [F][P][T][2] and int32
  * autos [F][I][T]; G2 from the exact int64 product rounded once to double;
  * rounding to a multiple of 2^k only for k >= 1, ties to even in integer

@@ -18,7 +18,7 @@ from ._lib import (BSG_ECAPACITY, BSG_ECORRUPT, BSG_EHIP, BSG_EINVAL, BSG_OK, Bs
                    Header)
 
 __all__ = [
-    "round_to_noise", "round_to_noise_i32", "bitshuffle", "bitunshuffle", "compress_bound", "workspace_size",
+    "round_to_noise", "round_to_noise_i32", "noise_compensation", "round_to_noise_scaled", "bitshuffle", "bitunshuffle", "compress_bound", "workspace_size",
     "compress", "round_compress", "decompress", "block_elems", "read_header", "BsgError",
     "compress_sync", "decompress_sync", "BSG_OK", "BSG_EINVAL", "BSG_ECAPACITY",
     "BSG_ECORRUPT", "BSG_EHIP", "load", "BatchPlan",
@@ -77,6 +77,46 @@ def round_to_noise(vis: torch.Tensor, autos: torch.Tensor, n_samples: float, f: 
     _lib.check(_lib.lib().bsg_round_to_noise(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
                                               _ptr(prod_map), float(n_samples), float(f),
                                               _stream_ptr(stream)), "round_to_noise")
+    return out
+
+
+def _vis_autos(vis, autos):
+    if vis.dtype != torch.complex64 or autos.dtype != torch.float32:
+        raise TypeError("vis must be complex64 and autos float32")
+    F, I, T = autos.shape
+    if tuple(vis.shape) != (F, I * (I + 1) // 2, T):
+        raise ValueError(f"vis {tuple(vis.shape)} does not match autos {tuple(autos.shape)}")
+    return F, I, T
+
+
+def noise_compensation(vis: torch.Tensor, autos: torch.Tensor, prod_map: torch.Tensor | None = None,
+                       out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Per-(frequency, time) factor on f (float64 (F, T)) that compensates
+    the diagonal noise model (Section 3.2)."""
+    _require_device(vis, autos, prod_map, out)
+    F, I, T = _vis_autos(vis, autos)
+    if out is None:
+        out = torch.empty((F, T), dtype=torch.float64, device=vis.device)
+    _lib.check(_lib.lib().bsg_noise_compensation(_ptr(vis), _ptr(autos), F, I, T, _ptr(prod_map),
+                                                  _ptr(out), _stream_ptr(stream)),
+               "noise_compensation")
+    return out
+
+
+def round_to_noise_scaled(vis: torch.Tensor, autos: torch.Tensor, n_samples: float, f: float,
+                          scale: torch.Tensor, out: torch.Tensor | None = None,
+                          prod_map: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """round_to_noise with G2 multiplied by scale[f][t] (float64 (F, T))."""
+    _require_device(vis, autos, scale, out, prod_map)
+    F, I, T = _vis_autos(vis, autos)
+    if scale.dtype != torch.float64 or tuple(scale.shape) != (F, T):
+        raise ValueError("scale must be float64 (F, T)")
+    if out is None:
+        out = torch.empty_like(vis)
+    _lib.check(_lib.lib().bsg_round_to_noise_scaled(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
+                                                     _ptr(prod_map), float(n_samples), float(f),
+                                                     _ptr(scale), _stream_ptr(stream)),
+               "round_to_noise_scaled")
     return out
 
 

@@ -24,6 +24,7 @@ EXPORTS = (
     "bsg_compress_lz4", "bsg_round_compress_lz4", "bsg_decompress_lz4", "bsg_read_header",
     "bsg_batch_table_bytes", "bsg_batch_build_table", "bsg_batch_workspace_size",
     "bsg_batch_compress", "bsg_batch_decompress", "bsg_round_to_noise_i32",
+    "bsg_noise_compensation", "bsg_round_to_noise_scaled",
 )
 
 
@@ -67,6 +68,10 @@ def _lib():
         L.bsg_round_to_noise.restype = i32
         L.bsg_round_to_noise_i32.argtypes = [vp, vp, vp, i64, i64, i64, vp, dbl, dbl, vp]
         L.bsg_round_to_noise_i32.restype = i32
+        L.bsg_noise_compensation.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp]
+        L.bsg_noise_compensation.restype = i32
+        L.bsg_round_to_noise_scaled.argtypes = [vp, vp, vp, i64, i64, i64, vp, dbl, dbl, vp, vp]
+        L.bsg_round_to_noise_scaled.restype = i32
         for f in (L.bsg_bitshuffle, L.bsg_bitunshuffle):
             f.argtypes = [vp, vp, i64, i64, i64, vp]
             f.restype = i32

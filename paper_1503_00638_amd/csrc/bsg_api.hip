@@ -54,6 +54,7 @@ inline RoundParams make_round(const float *autos, const int32_t *prod_map, int64
     RoundParams rp;
     rp.autos = autos;
     rp.autos_i32 = nullptr;
+    rp.fscale = nullptr;
     rp.prod_map = prod_map;
     rp.F = F;
     rp.I = I;
@@ -101,6 +102,37 @@ int bsg_round_to_noise(const void *vis_in, void *vis_out, const float *autos, in
     if (!vis_in || !vis_out || !autos) return BSG_EINVAL;
     if ((uintptr_t)vis_in % 8 || (uintptr_t)vis_out % 8 || (uintptr_t)autos % 4) return BSG_EINVAL;
     const RoundParams rp = make_round(autos, prod_map, F, I, T, n_samples, f);
+    return hip_status(launch_round(static_cast<const float *>(vis_in), static_cast<float *>(vis_out),
+                                   rp, static_cast<hipStream_t>(stream)));
+}
+
+int bsg_noise_compensation(const void *vis, const float *autos, int64_t F, int64_t I, int64_t T,
+                           const int32_t *prod_map, double *scale, void *stream)
+{
+    if (F < 0 || I < 0 || T < 0) return BSG_EINVAL;
+    if (F * T == 0) return BSG_OK;
+    if (!scale || (uintptr_t)scale % 8) return BSG_EINVAL;
+    const int64_t P = I * (I + 1) / 2;
+    if (P > 0 && (!vis || !autos || (uintptr_t)vis % 8 || (uintptr_t)autos % 4)) return BSG_EINVAL;
+    if (F > (int64_t)UINT32_MAX || (T + 63) / 64 > 65535) return BSG_EINVAL;
+    const RoundParams rp = make_round(autos, prod_map, F, I, T, 1.0, 0.0);
+    return hip_status(launch_noise_comp(static_cast<const float *>(vis), rp, scale,
+                                        static_cast<hipStream_t>(stream)));
+}
+
+int bsg_round_to_noise_scaled(const void *vis_in, void *vis_out, const float *autos, int64_t F,
+                              int64_t I, int64_t T, const int32_t *prod_map, double n_samples,
+                              double f, const double *scale, void *stream)
+{
+    if (!round_args_ok(F, I, T, n_samples, f)) return BSG_EINVAL;
+    const int64_t P = I * (I + 1) / 2;
+    if (F * P * T == 0) return BSG_OK;
+    if (!vis_in || !vis_out || !autos || !scale) return BSG_EINVAL;
+    if ((uintptr_t)vis_in % 8 || (uintptr_t)vis_out % 8 || (uintptr_t)autos % 4 ||
+        (uintptr_t)scale % 8)
+        return BSG_EINVAL;
+    RoundParams rp = make_round(autos, prod_map, F, I, T, n_samples, f);
+    rp.fscale = scale;
     return hip_status(launch_round(static_cast<const float *>(vis_in), static_cast<float *>(vis_out),
                                    rp, static_cast<hipStream_t>(stream)));
 }

@@ -155,6 +155,7 @@ __device__ __forceinline__ void unpack_e1(const uint32_t (&d)[32], uint32_t (&w)
 struct RoundParams {
     const float *autos;     // [F][I][T] (float visibilities)
     const int32_t *autos_i32; // [F][I][T] (integer visibilities)
+    const double *fscale;     // [F][T] factor on G2 (noise-model compensation) or nullptr
     const int32_t *prod_map; // [P][2] or nullptr (upper triangle row major)
     int64_t F, I, T, P;
     double c;      // (12 f) / (2 N): G2 = (V_ii V_jj) c for crosses
@@ -166,6 +167,7 @@ struct RoundParams {
 // ---------------------------------------------------------------------------
 hipError_t launch_round(const float *vin, float *vout, const RoundParams &rp, hipStream_t s);
 hipError_t launch_round_i32(const int32_t *vin, int32_t *vout, const RoundParams &rp, hipStream_t s);
+hipError_t launch_noise_comp(const float *vis, const RoundParams &rp, double *scale, hipStream_t s);
 hipError_t launch_shuffle(const uint8_t *in, uint8_t *out, const Layout &L, bool inverse,
                           hipStream_t s);
 hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int64_t cap,

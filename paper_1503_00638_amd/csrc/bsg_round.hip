@@ -59,6 +59,46 @@ __global__ __launch_bounds__(256) void k_round_i32(const int2 *__restrict__ vin,
     }
 }
 
+// Compensation of the diagonal noise model (Section 3.2): per (frequency,
+// time) the minimum over cross products of 1 - |V_ij|^2 / (V_ii V_jj), in
+// double and in that order (products with V_ii V_jj not positive and finite
+// skipped, 1 when none is left).  A workgroup takes one frequency and 64
+// times; its 4 wavefronts walk a quarter of the products each (lanes =
+// times, so every load is coalesced) and the 4 partial minima meet in LDS.
+__global__ __launch_bounds__(256) void k_noise_comp(const float2 *__restrict__ vis, RoundParams rp,
+                                                    double *__restrict__ scale)
+{
+    __shared__ double part[4][kWave];
+    const int tl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t fr = blockIdx.x;
+    const int64_t t = int64_t(blockIdx.y) * kWave + tl;
+    double m = 1.0;
+    const int64_t p0 = rp.P * q / 4, p1 = rp.P * (q + 1) / 4;
+    if (t < rp.T && p0 < p1) {
+        VisCursor c = cursor_at(rp, (fr * rp.P + p0) * rp.T + t);
+        for (int64_t p = p0;;) {
+            if (c.i != c.j) {
+                const double ab = (double)rp.autos[c.row_i + c.t] * (double)rp.autos[c.row_j + c.t];
+                if (ab > 0.0 && ab != __builtin_inf()) {
+                    const float2 v = vis[(fr * rp.P + p) * rp.T + t];
+                    const double term =
+                        1.0 - ((double)v.x * (double)v.x + (double)v.y * (double)v.y) / ab;
+                    if (term < m) m = term; // a NaN term never wins
+                }
+            }
+            if (++p == p1) break;
+            cursor_next_product(rp, c);
+        }
+    }
+    part[q][tl] = m;
+    __syncthreads();
+    if (q == 0 && t < rp.T) {
+        for (int k = 1; k < 4; ++k)
+            if (part[k][tl] < m) m = part[k][tl];
+        scale[fr * rp.T + t] = m;
+    }
+}
+
 } // namespace
 
 hipError_t launch_round(const float *vin, float *vout, const RoundParams &rp, hipStream_t s)
@@ -82,6 +122,15 @@ hipError_t launch_round_i32(const int32_t *vin, int32_t *vout, const RoundParams
     hipLaunchKernelGGL(k_round_i32, dim3((unsigned)blocks), dim3(256), 0, s,
                        reinterpret_cast<const int2 *>(vin), reinterpret_cast<int2 *>(vout), rp,
                        n_complex);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise_comp(const float *vis, const RoundParams &rp, double *scale, hipStream_t s)
+{
+    if (rp.F * rp.T == 0) return hipSuccess;
+    const dim3 grid((unsigned)rp.F, (unsigned)((rp.T + kWave - 1) / kWave));
+    hipLaunchKernelGGL(k_noise_comp, grid, dim3(256), 0, s, reinterpret_cast<const float2 *>(vis),
+                       rp, scale);
     return hipGetLastError();
 }
 

@@ -57,12 +57,14 @@ __device__ __forceinline__ uint32_t round_noise_bits(uint32_t x, double G2)
     return round_bits(x, granularity_k(G2));
 }
 
-// One complex visibility.  ai = V_ii, aj = V_jj at the same (f, t).  Both
+// One complex visibility.  ai = V_ii, aj = V_jj at the same (f, t); sc is
+// the factor on G2 at that (f, t) (1 without compensation).  Both
 // components of a cross product share one G2 and one k.
 __device__ __forceinline__ float2 round_complex(float2 v, float ai, float aj, bool is_auto,
-                                                const RoundParams &rp)
+                                                const RoundParams &rp, double sc = 1.0)
 {
-    const double G2 = ((double)ai * (double)aj) * (is_auto ? rp.c_auto : rp.c);
+    double G2 = ((double)ai * (double)aj) * (is_auto ? rp.c_auto : rp.c);
+    if (rp.fscale) G2 *= sc;
     if (!(G2 > 0.0) || G2 == __builtin_inf()) return v;
     const int k = granularity_k(G2);
     float2 o;
@@ -142,7 +144,8 @@ __device__ __forceinline__ float2 round_at(float2 v, const VisCursor &c, const R
 {
     const float ai = rp.autos[c.row_i + c.t];
     const float aj = rp.autos[c.row_j + c.t];
-    return round_complex(v, ai, aj, c.i == c.j, rp);
+    const double sc = rp.fscale ? rp.fscale[c.fr * rp.T + c.t] : 1.0;
+    return round_complex(v, ai, aj, c.i == c.j, rp, sc);
 }
 
 // Integer visibilities: the nearest multiple of 2^k, ties to the even
@@ -182,8 +185,17 @@ __device__ __forceinline__ uint32_t round_element(uint32_t x, int64_t e, const R
     const VisCursor c = cursor_at(rp, e >> 1);
     const float ai = rp.autos[c.row_i + c.t];
     const float aj = rp.autos[c.row_j + c.t];
-    if (c.i != c.j) return round_noise_bits(x, ((double)ai * (double)aj) * rp.c);
-    if ((e & 1) == 0) return round_noise_bits(x, ((double)ai * (double)ai) * rp.c_auto);
+    const double sc = rp.fscale ? rp.fscale[c.fr * rp.T + c.t] : 1.0;
+    if (c.i != c.j) {
+        double G2 = ((double)ai * (double)aj) * rp.c;
+        if (rp.fscale) G2 *= sc;
+        return round_noise_bits(x, G2);
+    }
+    if ((e & 1) == 0) {
+        double G2 = ((double)ai * (double)ai) * rp.c_auto;
+        if (rp.fscale) G2 *= sc;
+        return round_noise_bits(x, G2);
+    }
     return x;
 }
 

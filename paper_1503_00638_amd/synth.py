@@ -92,6 +92,22 @@ def gen_vis(F: int, I: int, T: int, seed: int, n_samples: float = N_SAMPLES_DEFA
     return vis, autos
 
 
+def gen_vis_point_source(F: int, I: int, T: int, seed: int, source: float = 0.4,
+                         n_samples: float = N_SAMPLES_DEFAULT):
+    """Visibilities dominated by one unresolved source at zenith with
+    calibrated gains (the case Section 3.1 uses to show correlated noise):
+    every product gains the same real term S = source x the mean receiver
+    power, autos included, on top of the noise model above.  Returns
+    (vis complex64 (F, P, T), autos float32 (F, I, T))."""
+    vis, _ = gen_vis(F, I, T, seed, n_samples)
+    vf = vis.view(np.float32).reshape(F, -1, T, 2)
+    vf[..., 0] += np.float32(source * 1e3)
+    pairs = product_pairs(I)
+    is_auto = pairs[:, 0] == pairs[:, 1]
+    autos = np.ascontiguousarray(vf[..., 0][:, is_auto, :])
+    return vis, autos
+
+
 def gen_vis_int(F: int, I: int, T: int, seed: int, n_samples: float = N_SAMPLES_DEFAULT,
                 scale: float = 1024.0):
     """Integer visibilities, the data type of the paper's correlator output:

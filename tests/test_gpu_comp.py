@@ -1,0 +1,87 @@
+"""GPU parity for the compensation of the diagonal noise model (Section
+3.2): the per-(frequency, time) factor and the rounding that uses it equal
+the oracle bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_00638_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = synth.N_SAMPLES_DEFAULT
+
+
+@pytest.fixture(scope="module")
+def bsg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1503_00638_amd as m
+    m.load()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CASES = [(4, 8, 64, 0, 0.4), (3, 5, 7, 1, 0.0), (2, 16, 130, 2, 2.0), (1, 1, 5, 3, 0.4),
+         (2, 2, 65, 4, 1.0), (5, 3, 1, 5, 0.4), (16, 8, 64, 6, 0.1)]
+
+
+@pytest.mark.parametrize("F,I,T,seed,source", CASES)
+def test_compensation_factor_parity(bsg, F, I, T, seed, source):
+    vis, autos = synth.gen_vis_point_source(F, I, T, seed, source)
+    ref = oracle.noise_compensation(vis, autos)
+    got = host(bsg.noise_compensation(dev(vis), dev(autos)))
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("F,I,T,seed,source", CASES)
+def test_compensated_rounding_parity(bsg, F, I, T, seed, source):
+    vis, autos = synth.gen_vis_point_source(F, I, T, seed, source)
+    m = oracle.noise_compensation(vis, autos)
+    for f in (0.01, 1e-3):
+        ref = oracle.round_to_noise_scaled(vis, autos, N, f, m)
+        got = host(bsg.round_to_noise_scaled(dev(vis), dev(autos), N, f, dev(m)))
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), f
+    # the device factor feeds the device rounding directly
+    dv, da = dev(vis), dev(autos)
+    got = host(bsg.round_to_noise_scaled(dv, da, N, 0.01, bsg.noise_compensation(dv, da)))
+    assert np.array_equal(got.view(np.uint32), oracle.round_to_noise_scaled(vis, autos, N, 0.01, m).view(np.uint32))
+
+
+def test_compensation_degenerate_inputs(bsg):
+    vis, autos = synth.gen_vis_point_source(3, 6, 40, 9, 0.4)
+    autos[0, 1, :5] = [0.0, -3.0, np.nan, np.inf, 1e-40]
+    autos[1, :, 7] = 0.0
+    vis.view(np.float32).reshape(-1)[::17] = np.nan
+    ref = oracle.noise_compensation(vis, autos)
+    got = host(bsg.noise_compensation(dev(vis), dev(autos)))
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+    ref_r = oracle.round_to_noise_scaled(vis, autos, N, 0.01, ref)
+    got_r = host(bsg.round_to_noise_scaled(dev(vis), dev(autos), N, 0.01, dev(ref)))
+    assert np.array_equal(got_r.view(np.uint32), ref_r.view(np.uint32))
+
+
+def test_unit_scale_is_plain_rounding(bsg):
+    vis, autos = synth.gen_vis(4, 8, 64, 0)
+    ones = torch.ones((4, 64), dtype=torch.float64, device="cuda:0")
+    a = host(bsg.round_to_noise_scaled(dev(vis), dev(autos), N, 0.01, ones))
+    b = host(bsg.round_to_noise(dev(vis), dev(autos), N, 0.01))
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_compensation_prod_map(bsg):
+    vis, autos = synth.gen_vis_point_source(2, 5, 16, 10, 0.4)
+    P = vis.shape[1]
+    pm = np.ascontiguousarray(synth.product_pairs(5)[np.random.default_rng(2).permutation(P)])
+    ref = oracle.noise_compensation(vis, autos, prod_map=pm)
+    got = host(bsg.noise_compensation(dev(vis), dev(autos), prod_map=dev(pm)))
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
