@@ -88,7 +88,8 @@ def main(argv=None):
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale)")
-    ap.add_argument("--workload", choices=("chunk", "batch", "serve", "sweep"), default="chunk",
+    ap.add_argument("--workload", choices=("chunk", "batch", "serve", "sweep", "filters"),
+                    default="chunk",
                     help="chunk: one 2.16 GB CHIME-shaped chunk (default); batch: 4096 "
                          "independent chunks; serve: Poisson request stream; sweep: bit "
                          "transpose of 1 GiB at every element size and block size")
@@ -114,6 +115,8 @@ def main(argv=None):
         return bench_serve(args, torch, bsg)
     if args.workload == "sweep":
         return bench_sweep(args, torch, bsg)
+    if args.workload == "filters":
+        return bench_filters(args, torch, bsg)
 
     w = WORKLOAD
     dev = torch.device("cuda:0")
@@ -445,6 +448,56 @@ def bench_sweep(args, torch, bsg):
                      "unit": "GB/s", "frac": best["forward_hbm_frac"], "traffic": None,
                      "algorithmic_bytes_per_launch": 2 * nbytes},
         "slowest_case": worst,
+        "source_digest": source_digest(),
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_filters(args, torch, bsg):
+    """The paper's comparison (Table t:performance): the same rounded
+    CHIME-shaped chunk compressed with the bit transpose and with the
+    Blosc-style byte shuffle before the same LZ4; ratio and throughput."""
+    from paper_1503_00638_amd import synth
+
+    w = WORKLOAD
+    dev = torch.device("cuda:0")
+    vis, autos = synth.gen_vis(w["F"], w["I"], w["T"], w["seed"], w["N"])
+    dvis, dautos = torch.from_numpy(vis).to(dev), torch.from_numpy(autos).to(dev)
+    r = bsg.round_to_noise(dvis, dautos, w["N"], w["f"]).view(torch.uint8).reshape(-1)
+    del dvis
+    U = r.numel()
+    n, nb = U // 4, w["block_bytes"] // 4
+    out = torch.empty(bsg.compress_bound(n, 4, nb), dtype=torch.uint8, device=dev)
+    ws = torch.empty(bsg.workspace_size(n, 4, nb), dtype=torch.uint8, device=dev)
+    nbytes = torch.empty(1, dtype=torch.int64, device=dev)
+    dec = torch.empty(U, dtype=torch.uint8, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    rows = {}
+    for name, flt in (("bitshuffle", bsg.BSG_FILTER_BIT), ("byteshuffle", bsg.BSG_FILTER_BYTE)):
+        bsg.compress(r, 4, nb, out=out, workspace=ws, nbytes=nbytes, filter=flt)
+        m = int(nbytes.item())
+        c_ms = _time_calls(torch, lambda: bsg.compress(r, 4, nb, out=out, workspace=ws,
+                                                         nbytes=nbytes, filter=flt),
+                           args.steps, args.warmup)
+        d_ms = _time_calls(torch, lambda: bsg.decompress(out, m, n, 4, nb, out=dec, status=status,
+                                                           filter=flt), args.steps, args.warmup)
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0 and torch.equal(dec, r), name
+        rows[name] = {"ratio": round(m / U, 5),
+                      "compress_GBps": round(U / (float(np.median(c_ms)) * 1e-3) / 1e9, 2),
+                      "decompress_GBps": round(U / (float(np.median(d_ms)) * 1e-3) / 1e9, 2)}
+    res = {
+        "metric": "uncompressed GB/s (compress & decompress) + % HBM peak; p50/p99 latency",
+        "value": rows["bitshuffle"]["decompress_GBps"], "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "filter comparison: the rounded CHIME-Pathfinder-shaped chunk "
+                               "(2.16 GB, f=0.01) with the bit transpose vs the Blosc-style byte "
+                               "shuffle before the same per-block LZ4, 8192-byte blocks",
+                   "parallelism": "single GPU"},
+        "filters": rows,
+        "paper_ratios_for_context": {"bitshuffle_lz4": 0.279, "blosc_lz4": 0.473},
         "source_digest": source_digest(),
     }
     print(json.dumps(res), flush=True)

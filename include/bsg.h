@@ -51,6 +51,14 @@ extern "C" {
  *   payload: the LZ4 blocks, concatenated, off[0] = 0
  *   raw tail: the last (n mod 8) elements, verbatim                       */
 #define BSG_MAGIC 0x31475342u /* bytes "BSG1" */
+#define BSG_MAGIC_BYTE 0x31425342u /* bytes "BSB1": byte-shuffled stream */
+
+/* Block filters applied before LZ4: the bit transpose of Section 4.2 (the
+ * method), or the byte shuffle of Blosc-style compressors (the comparison
+ * of Section 4.1 and Table t:performance): byte k of element i of a block
+ * goes to byte k * n_B + i. */
+#define BSG_FILTER_BIT 0
+#define BSG_FILTER_BYTE 1
 typedef struct bsg_header {
     uint32_t magic;
     uint32_t elem_size;
@@ -141,6 +149,13 @@ int bsg_bitshuffle(const void *in, void *out, int64_t n, int64_t elem_size, int6
                    void *stream);
 int bsg_bitunshuffle(const void *in, void *out, int64_t n, int64_t elem_size,
                      int64_t block_size, void *stream);
+
+/* The byte shuffle within blocks (same blocks, partial block and raw tail
+ * as bsg_bitshuffle), and its inverse. */
+int bsg_byteshuffle(const void *in, void *out, int64_t n, int64_t elem_size, int64_t block_size,
+                    void *stream);
+int bsg_byteunshuffle(const void *in, void *out, int64_t n, int64_t elem_size,
+                      int64_t block_size, void *stream);
 
 /* ---- Stage 2b: bit transpose + per-block LZ4 (Section 4.2) ------------
  * Exact worst-case size of the compressed stream (host, no device work). */
@@ -250,6 +265,19 @@ int bsg_batch_compress(const void *host_table, const void *d_table, int64_t *d_n
  * checks and the same memory bounds as bsg_decompress_lz4. */
 int bsg_batch_decompress(const void *host_table, const void *d_table, int32_t *d_status,
                          int32_t waves_per_cu, void *stream);
+
+/* bsg_compress_lz4 / bsg_decompress_lz4 with the block filter chosen by
+ * `filter` (BSG_FILTER_BIT gives exactly those calls; BSG_FILTER_BYTE
+ * byte-shuffles each block instead and marks the stream with
+ * BSG_MAGIC_BYTE).  Same workspace, bounds and errors; decompression
+ * rejects a stream whose magic does not match the filter. */
+int bsg_compress_lz4_filter(const void *in, void *out, int64_t n, int64_t elem_size,
+                            int64_t block_size, int32_t filter, int64_t out_capacity,
+                            int64_t *d_out_nbytes, void *workspace, int64_t workspace_bytes,
+                            void *stream);
+int bsg_decompress_lz4_filter(const void *in, int64_t in_nbytes, void *out, int64_t n,
+                              int64_t elem_size, int64_t block_size, int32_t filter,
+                              int32_t *d_status, void *stream);
 
 /* Parse a stream header from HOST memory (no device work). */
 int bsg_read_header(const void *host_bytes, int64_t nbytes, bsg_header *hdr);

@@ -71,6 +71,13 @@ def lib():
         L.oracle_compress.restype = i64
         L.oracle_decompress.argtypes = [vp, i64, vp, i64, i64, i64, i32]
         L.oracle_decompress.restype = i64
+        for name in ("oracle_byteshuffle", "oracle_byteunshuffle"):
+            getattr(L, name).argtypes = [vp, vp, i64, i64, i64, i32]
+            getattr(L, name).restype = i32
+        L.oracle_compress_filter.argtypes = [vp, vp, i64, i64, i64, i32, i64, i32]
+        L.oracle_compress_filter.restype = i64
+        L.oracle_decompress_filter.argtypes = [vp, i64, vp, i64, i64, i64, i32, i32]
+        L.oracle_decompress_filter.restype = i64
         L.oracle_max_threads.argtypes = []
         L.oracle_max_threads.restype = i32
         _lib = L
@@ -199,6 +206,14 @@ def bitunshuffle(data: np.ndarray, elem_size: int, block_size: int = 0, nthreads
     return _transpose(lib().oracle_bitunshuffle, data, elem_size, block_size, nthreads)
 
 
+def byteshuffle(data: np.ndarray, elem_size: int, block_size: int = 0, nthreads: int = 0) -> np.ndarray:
+    return _transpose(lib().oracle_byteshuffle, data, elem_size, block_size, nthreads)
+
+
+def byteunshuffle(data: np.ndarray, elem_size: int, block_size: int = 0, nthreads: int = 0) -> np.ndarray:
+    return _transpose(lib().oracle_byteunshuffle, data, elem_size, block_size, nthreads)
+
+
 def lz4_compress_block(block: np.ndarray) -> bytes:
     src = _as_u8(block)
     cap = src.size + src.size // 255 + 16
@@ -222,7 +237,9 @@ def compress_bound(n: int, elem_size: int, block_size: int = 0) -> int:
     return int(lib().oracle_compress_bound(n, elem_size, block_size))
 
 
-def compress(data: np.ndarray, elem_size: int, block_size: int = 0, nthreads: int = 0) -> np.ndarray:
+def compress(data: np.ndarray, elem_size: int, block_size: int = 0, nthreads: int = 0,
+             filter: int = 0) -> np.ndarray:
+    """Stream of data; filter 0 = bit transpose (the method), 1 = byte shuffle."""
     src = _as_u8(data)
     n = src.size // elem_size
     if n * elem_size != src.size:
@@ -231,17 +248,19 @@ def compress(data: np.ndarray, elem_size: int, block_size: int = 0, nthreads: in
     if cap < 0:
         raise OracleError(cap, "compress_bound")
     out = np.empty(cap, dtype=np.uint8)
-    m = lib().oracle_compress(_ptr(src), _ptr(out), n, elem_size, block_size, cap, nthreads)
+    m = lib().oracle_compress_filter(_ptr(src), _ptr(out), n, elem_size, block_size, int(filter),
+                                     cap, nthreads)
     if m < 0:
         raise OracleError(m, "compress")
     return out[:m]
 
 
 def decompress(stream: np.ndarray, n: int, elem_size: int, block_size: int = 0,
-               nthreads: int = 0) -> np.ndarray:
+               nthreads: int = 0, filter: int = 0) -> np.ndarray:
     src = _as_u8(stream)
     out = np.empty(max(n * elem_size, 1), dtype=np.uint8)
-    rc = lib().oracle_decompress(_ptr(src), src.size, _ptr(out), n, elem_size, block_size, nthreads)
+    rc = lib().oracle_decompress_filter(_ptr(src), src.size, _ptr(out), n, elem_size, block_size,
+                                        int(filter), nthreads)
     if rc != 0:
         raise OracleError(rc, "decompress")
     return out[: n * elem_size]

@@ -19,6 +19,7 @@
 
 /* ---- constants of the stream format and of the fixed LZ4 match rule ---- */
 #define STREAM_MAGIC 0x31475342u /* bytes "BSG1" */
+#define STREAM_MAGIC_BYTE 0x31425342u /* bytes "BSB1": byte-shuffled blocks */
 #define HEADER_BYTES 24
 #define DEFAULT_BLOCK_BYTES 8192
 #define MAX_BLOCK_BYTES 65536 /* LZ4 offsets are 16-bit */
@@ -420,8 +421,42 @@ static void bitunshuffle_block(const uint8_t *in, uint8_t *out, int64_t nb, int6
         }
 }
 
+/* The byte shuffle of Blosc-style compressors (the comparison of Section
+ * 4.1 / Table t:performance): the (nb x E) byte matrix of a block is
+ * transposed, byte k of element i going to byte k * nb + i. */
+static void byteshuffle_block(const uint8_t *in, uint8_t *out, int64_t nb, int64_t E)
+{
+    for (int64_t i = 0; i < nb; i++)
+        for (int64_t k = 0; k < E; k++)
+            out[k * nb + i] = in[i * E + k];
+}
+
+static void byteunshuffle_block(const uint8_t *in, uint8_t *out, int64_t nb, int64_t E)
+{
+    for (int64_t i = 0; i < nb; i++)
+        for (int64_t k = 0; k < E; k++)
+            out[i * E + k] = in[k * nb + i];
+}
+
+/* filter 0: bit transpose (the method); 1: byte shuffle (the comparison) */
+static void filter_block(const uint8_t *in, uint8_t *out, int64_t nb, int64_t E, int filter,
+                         int inverse)
+{
+    if (filter == 1) {
+        if (inverse)
+            byteunshuffle_block(in, out, nb, E);
+        else
+            byteshuffle_block(in, out, nb, E);
+    } else {
+        if (inverse)
+            bitunshuffle_block(in, out, nb, E);
+        else
+            bitshuffle_block(in, out, nb, E);
+    }
+}
+
 static int transpose_blocks(const uint8_t *in, uint8_t *out, int64_t n, int64_t E,
-                            int64_t block_size, int nthreads, int inverse)
+                            int64_t block_size, int nthreads, int inverse, int filter)
 {
     const int64_t nb = oracle_block_elems(E, block_size);
     if (nb < 0 || n < 0)
@@ -434,10 +469,7 @@ static int transpose_blocks(const uint8_t *in, uint8_t *out, int64_t n, int64_t 
     for (int64_t blk = 0; blk < n_blocks; blk++) {
         const int64_t elems = blk < n_full ? nb : last;
         const int64_t off = blk * nb * E;
-        if (inverse)
-            bitunshuffle_block(in + off, out + off, elems, E);
-        else
-            bitshuffle_block(in + off, out + off, elems, E);
+        filter_block(in + off, out + off, elems, E, filter, inverse);
     }
     if (tail)
         memcpy(out + (n - tail) * E, in + (n - tail) * E, (size_t)(tail * E));
@@ -447,13 +479,25 @@ static int transpose_blocks(const uint8_t *in, uint8_t *out, int64_t n, int64_t 
 int oracle_bitshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
                       int64_t block_size, int nthreads)
 {
-    return transpose_blocks(in, out, n, elem_size, block_size, nthreads, 0);
+    return transpose_blocks(in, out, n, elem_size, block_size, nthreads, 0, 0);
 }
 
 int oracle_bitunshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
                         int64_t block_size, int nthreads)
 {
-    return transpose_blocks(in, out, n, elem_size, block_size, nthreads, 1);
+    return transpose_blocks(in, out, n, elem_size, block_size, nthreads, 1, 0);
+}
+
+int oracle_byteshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                       int64_t block_size, int nthreads)
+{
+    return transpose_blocks(in, out, n, elem_size, block_size, nthreads, 0, 1);
+}
+
+int oracle_byteunshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                         int64_t block_size, int nthreads)
+{
+    return transpose_blocks(in, out, n, elem_size, block_size, nthreads, 1, 1);
 }
 
 /* ======================================================================
@@ -665,9 +709,11 @@ int64_t oracle_compress_bound(int64_t n, int64_t elem_size, int64_t block_size)
     return bound;
 }
 
-int64_t oracle_compress(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
-                        int64_t block_size, int64_t cap, int nthreads)
+int64_t oracle_compress_filter(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                               int64_t block_size, int filter, int64_t cap, int nthreads)
 {
+    if (filter != 0 && filter != 1)
+        return -1;
     const int64_t bound = oracle_compress_bound(n, elem_size, block_size);
     if (bound < 0 || (n > 0 && !in) || !out)
         return -1;
@@ -689,7 +735,7 @@ int64_t oracle_compress(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem
 #pragma omp for schedule(dynamic, 64)
         for (int64_t blk = 0; blk < n_blocks; blk++) {
             const int64_t elems = blk < n_full ? nb : last;
-            bitshuffle_block(in + blk * nb * E, tmp, elems, E);
+            filter_block(in + blk * nb * E, tmp, elems, E, filter, 0);
             size[blk] = oracle_lz4_compress_block(tmp, elems * E, slots + blk * slot, slot);
         }
         free(tmp);
@@ -709,7 +755,7 @@ int64_t oracle_compress(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem
         free(size);
         return -2;
     }
-    put_u32(out, STREAM_MAGIC);
+    put_u32(out, filter == 1 ? STREAM_MAGIC_BYTE : STREAM_MAGIC);
     put_u32(out + 4, (uint32_t)E);
     put_u64(out + 8, (uint64_t)n);
     put_u32(out + 16, (uint32_t)nb);
@@ -729,9 +775,17 @@ int64_t oracle_compress(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem
     return total;
 }
 
-int64_t oracle_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, int64_t n,
-                          int64_t elem_size, int64_t block_size, int nthreads)
+int64_t oracle_compress(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                        int64_t block_size, int64_t cap, int nthreads)
 {
+    return oracle_compress_filter(in, out, n, elem_size, block_size, 0, cap, nthreads);
+}
+
+int64_t oracle_decompress_filter(const uint8_t *in, int64_t in_nbytes, uint8_t *out, int64_t n,
+                                 int64_t elem_size, int64_t block_size, int filter, int nthreads)
+{
+    if (filter != 0 && filter != 1)
+        return -1;
     const int64_t nb = oracle_block_elems(elem_size, block_size);
     if (nb < 0 || n < 0 || !in || (n > 0 && !out) || nb * elem_size > MAX_BLOCK_BYTES)
         return -1;
@@ -741,7 +795,8 @@ int64_t oracle_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, in
     const int64_t table_end = HEADER_BYTES + 8 * (n_blocks + 1);
     if (in_nbytes < table_end)
         return -3;
-    if (get_u32(in) != STREAM_MAGIC || get_u32(in + 4) != (uint32_t)E ||
+    if (get_u32(in) != (filter == 1 ? STREAM_MAGIC_BYTE : STREAM_MAGIC) ||
+        get_u32(in + 4) != (uint32_t)E ||
         get_u64(in + 8) != (uint64_t)n || get_u32(in + 16) != (uint32_t)nb ||
         get_u32(in + 20) != (uint32_t)n_blocks)
         return -3;
@@ -767,7 +822,7 @@ int64_t oracle_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, in
                 bad = 1;
                 continue;
             }
-            bitunshuffle_block(tmp, out + blk * nb * E, elems, E);
+            filter_block(tmp, out + blk * nb * E, elems, E, filter, 1);
         }
         free(tmp);
     }
@@ -776,4 +831,10 @@ int64_t oracle_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, in
     if (tail)
         memcpy(out + (n - tail) * E, payload + payload_len, (size_t)(tail * E));
     return 0;
+}
+
+int64_t oracle_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, int64_t n,
+                          int64_t elem_size, int64_t block_size, int nthreads)
+{
+    return oracle_decompress_filter(in, in_nbytes, out, n, elem_size, block_size, 0, nthreads);
 }

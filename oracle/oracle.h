@@ -89,6 +89,19 @@ int64_t oracle_compress(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem
 int64_t oracle_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, int64_t n,
                           int64_t elem_size, int64_t block_size, int nthreads);
 
+/* The comparison filter (Section 4.1, Table t:performance): Blosc-style
+ * byte shuffle within the same blocks (byte k of element i -> k * nb + i),
+ * and streams whose blocks are byte-shuffled (filter 1, magic "BSB1")
+ * instead of bit-transposed (filter 0, identical to oracle_compress). */
+int oracle_byteshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                       int64_t block_size, int nthreads);
+int oracle_byteunshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                         int64_t block_size, int nthreads);
+int64_t oracle_compress_filter(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
+                               int64_t block_size, int filter, int64_t cap, int nthreads);
+int64_t oracle_decompress_filter(const uint8_t *in, int64_t in_nbytes, uint8_t *out, int64_t n,
+                                 int64_t elem_size, int64_t block_size, int filter, int nthreads);
+
 int oracle_max_threads(void);
 
 #ifdef __cplusplus

@@ -14,14 +14,15 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (BSG_ECAPACITY, BSG_ECORRUPT, BSG_EHIP, BSG_EINVAL, BSG_OK, BsgError,
-                   Header)
+from ._lib import (BSG_ECAPACITY, BSG_ECORRUPT, BSG_EHIP, BSG_EINVAL, BSG_FILTER_BIT,
+                   BSG_FILTER_BYTE, BSG_OK, BsgError, Header)
 
 __all__ = [
     "round_to_noise", "round_to_noise_i32", "noise_compensation", "round_to_noise_scaled", "bitshuffle", "bitunshuffle", "compress_bound", "workspace_size",
     "compress", "round_compress", "decompress", "block_elems", "read_header", "BsgError",
     "compress_sync", "decompress_sync", "BSG_OK", "BSG_EINVAL", "BSG_ECAPACITY",
-    "BSG_ECORRUPT", "BSG_EHIP", "load", "BatchPlan",
+    "BSG_ECORRUPT", "BSG_EHIP", "load", "BatchPlan", "byteshuffle", "byteunshuffle",
+    "BSG_FILTER_BIT", "BSG_FILTER_BYTE",
 ]
 
 
@@ -167,6 +168,19 @@ def bitunshuffle(x: torch.Tensor, elem_size: int, block_size: int = 0,
                       "bitunshuffle")
 
 
+def byteshuffle(x: torch.Tensor, elem_size: int, block_size: int = 0,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Blosc-style byte shuffle within blocks (the comparison filter)."""
+    return _transpose(_lib.lib().bsg_byteshuffle, x, elem_size, block_size, out, stream,
+                      "byteshuffle")
+
+
+def byteunshuffle(x: torch.Tensor, elem_size: int, block_size: int = 0,
+                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    return _transpose(_lib.lib().bsg_byteunshuffle, x, elem_size, block_size, out, stream,
+                      "byteunshuffle")
+
+
 def compress_bound(n: int, elem_size: int, block_size: int = 0) -> int:
     r = _lib.lib().bsg_compress_bound(n, elem_size, block_size)
     if r < 0:
@@ -190,7 +204,7 @@ def _alloc_ws(n, elem_size, block_size, device, workspace):
 
 def compress(x: torch.Tensor, elem_size: int, block_size: int = 0,
              out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
-             nbytes: torch.Tensor | None = None, stream=None):
+             nbytes: torch.Tensor | None = None, stream=None, filter: int = BSG_FILTER_BIT):
     """Enqueue compression of x.  Returns (out, nbytes): out is a uint8 buffer
     of compress_bound bytes (or the one given), nbytes a device int64 holding
     the stream length (or BSG_ECAPACITY) once the stream has run."""
@@ -205,9 +219,10 @@ def compress(x: torch.Tensor, elem_size: int, block_size: int = 0,
     workspace = _alloc_ws(n, elem_size, block_size, x.device, workspace)
     if nbytes is None:
         nbytes = torch.empty(1, dtype=torch.int64, device=x.device)
-    _lib.check(_lib.lib().bsg_compress_lz4(_ptr(x), _ptr(out), n, elem_size, block_size,
-                                            _nbytes(out), _ptr(nbytes), _ptr(workspace),
-                                            _nbytes(workspace), _stream_ptr(stream)),
+    _lib.check(_lib.lib().bsg_compress_lz4_filter(_ptr(x), _ptr(out), n, elem_size, block_size,
+                                                   int(filter), _nbytes(out), _ptr(nbytes),
+                                                   _ptr(workspace), _nbytes(workspace),
+                                                   _stream_ptr(stream)),
                "compress_lz4")
     return out, nbytes
 
@@ -235,7 +250,7 @@ def round_compress(vis: torch.Tensor, autos: torch.Tensor, n_samples: float, f: 
 
 def decompress(stream_bytes: torch.Tensor, in_nbytes: int, n: int, elem_size: int,
                block_size: int = 0, out: torch.Tensor | None = None,
-               status: torch.Tensor | None = None, stream=None):
+               status: torch.Tensor | None = None, stream=None, filter: int = BSG_FILTER_BIT):
     """Enqueue decompression.  Returns (out, status): status is a device int32
     that reads 0 on success and BSG_ECORRUPT otherwise."""
     _require_device(stream_bytes, out, status)
@@ -243,22 +258,25 @@ def decompress(stream_bytes: torch.Tensor, in_nbytes: int, n: int, elem_size: in
         out = torch.empty(max(n * elem_size, 1), dtype=torch.uint8, device=stream_bytes.device)
     if status is None:
         status = torch.zeros(1, dtype=torch.int32, device=stream_bytes.device)
-    _lib.check(_lib.lib().bsg_decompress_lz4(_ptr(stream_bytes), int(in_nbytes), _ptr(out), n,
-                                              elem_size, block_size, _ptr(status),
-                                              _stream_ptr(stream)), "decompress_lz4")
+    _lib.check(_lib.lib().bsg_decompress_lz4_filter(_ptr(stream_bytes), int(in_nbytes), _ptr(out),
+                                                     n, elem_size, block_size, int(filter),
+                                                     _ptr(status), _stream_ptr(stream)),
+               "decompress_lz4")
     return out, status
 
 
-def compress_sync(x: torch.Tensor, elem_size: int, block_size: int = 0) -> torch.Tensor:
-    out, nb = compress(x, elem_size, block_size)
+def compress_sync(x: torch.Tensor, elem_size: int, block_size: int = 0,
+                  filter: int = BSG_FILTER_BIT) -> torch.Tensor:
+    out, nb = compress(x, elem_size, block_size, filter=filter)
     m = int(nb.item())
     if m < 0:
         raise BsgError(m, "compress_lz4")
     return out[:m]
 
 
-def decompress_sync(s: torch.Tensor, n: int, elem_size: int, block_size: int = 0) -> torch.Tensor:
-    out, st = decompress(s, _nbytes(s), n, elem_size, block_size)
+def decompress_sync(s: torch.Tensor, n: int, elem_size: int, block_size: int = 0,
+                    filter: int = BSG_FILTER_BIT) -> torch.Tensor:
+    out, st = decompress(s, _nbytes(s), n, elem_size, block_size, filter=filter)
     code = int(st.item())
     if code != 0:
         raise BsgError(code, "decompress_lz4")

@@ -12,6 +12,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libbsg.so")
 
 BSG_OK = 0
+BSG_FILTER_BIT, BSG_FILTER_BYTE = 0, 1
 BSG_EINVAL = -1
 BSG_ECAPACITY = -2
 BSG_ECORRUPT = -3
@@ -24,7 +25,8 @@ EXPORTS = (
     "bsg_compress_lz4", "bsg_round_compress_lz4", "bsg_decompress_lz4", "bsg_read_header",
     "bsg_batch_table_bytes", "bsg_batch_build_table", "bsg_batch_workspace_size",
     "bsg_batch_compress", "bsg_batch_decompress", "bsg_round_to_noise_i32",
-    "bsg_noise_compensation", "bsg_round_to_noise_scaled",
+    "bsg_noise_compensation", "bsg_round_to_noise_scaled", "bsg_byteshuffle",
+    "bsg_byteunshuffle", "bsg_compress_lz4_filter", "bsg_decompress_lz4_filter",
 )
 
 
@@ -72,7 +74,7 @@ def _lib():
         L.bsg_noise_compensation.restype = i32
         L.bsg_round_to_noise_scaled.argtypes = [vp, vp, vp, i64, i64, i64, vp, dbl, dbl, vp, vp]
         L.bsg_round_to_noise_scaled.restype = i32
-        for f in (L.bsg_bitshuffle, L.bsg_bitunshuffle):
+        for f in (L.bsg_bitshuffle, L.bsg_bitunshuffle, L.bsg_byteshuffle, L.bsg_byteunshuffle):
             f.argtypes = [vp, vp, i64, i64, i64, vp]
             f.restype = i32
         L.bsg_compress_bound.argtypes = [i64, i64, i64]
@@ -86,6 +88,11 @@ def _lib():
         L.bsg_round_compress_lz4.restype = i32
         L.bsg_decompress_lz4.argtypes = [vp, i64, vp, i64, i64, i64, vp, vp]
         L.bsg_decompress_lz4.restype = i32
+        L.bsg_compress_lz4_filter.argtypes = [vp, vp, i64, i64, i64, ctypes.c_int32, i64, vp, vp, i64,
+                                              vp]
+        L.bsg_compress_lz4_filter.restype = i32
+        L.bsg_decompress_lz4_filter.argtypes = [vp, i64, vp, i64, i64, i64, ctypes.c_int32, vp, vp]
+        L.bsg_decompress_lz4_filter.restype = i32
         L.bsg_read_header.argtypes = [vp, i64, ctypes.POINTER(Header)]
         L.bsg_read_header.restype = i32
         L.bsg_batch_table_bytes.argtypes = [ctypes.c_int32]

@@ -164,6 +164,30 @@ static int shuffle_common(const void *in, void *out, int64_t n, int64_t E, int64
                                      L, inverse, static_cast<hipStream_t>(stream)));
 }
 
+int bsg_byteshuffle(const void *in, void *out, int64_t n, int64_t elem_size, int64_t block_size,
+                    void *stream)
+{
+    Layout L;
+    if (!make_layout(n, elem_size, block_size, &L)) return BSG_EINVAL;
+    if (n == 0) return BSG_OK;
+    if (!in || !out || (uintptr_t)out % 4) return BSG_EINVAL;
+    return hip_status(launch_byteshuffle(static_cast<const uint8_t *>(in),
+                                         static_cast<uint8_t *>(out), L, false,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+int bsg_byteunshuffle(const void *in, void *out, int64_t n, int64_t elem_size,
+                      int64_t block_size, void *stream)
+{
+    Layout L;
+    if (!make_layout(n, elem_size, block_size, &L)) return BSG_EINVAL;
+    if (n == 0) return BSG_OK;
+    if (!in || !out || (uintptr_t)out % 4) return BSG_EINVAL;
+    return hip_status(launch_byteshuffle(static_cast<const uint8_t *>(in),
+                                         static_cast<uint8_t *>(out), L, true,
+                                         static_cast<hipStream_t>(stream)));
+}
+
 int bsg_bitshuffle(const void *in, void *out, int64_t n, int64_t elem_size, int64_t block_size,
                    void *stream)
 {
@@ -196,8 +220,9 @@ int64_t bsg_compress_workspace_size(int64_t n, int64_t elem_size, int64_t block_
 
 static int compress_common(const void *in, void *out, const Layout &L, int64_t out_capacity,
                            int64_t *d_out_nbytes, void *workspace, int64_t workspace_bytes,
-                           const RoundParams *rp, void *stream)
+                           const RoundParams *rp, void *stream, int filter = BSG_FILTER_BIT)
 {
+    if (filter != BSG_FILTER_BIT && filter != BSG_FILTER_BYTE) return BSG_EINVAL;
     if (L.block_bytes() > BSG_MAX_BLOCK_BYTES) return BSG_EINVAL;
     if (!out || !d_out_nbytes || !workspace || (L.n > 0 && !in)) return BSG_EINVAL;
     if ((uintptr_t)out % 8 || (uintptr_t)workspace % 256 || (uintptr_t)d_out_nbytes % 8)
@@ -206,7 +231,7 @@ static int compress_common(const void *in, void *out, const Layout &L, int64_t o
     if (out_capacity < fixed_stream_bytes(L)) return BSG_ECAPACITY;
     return hip_status(launch_compress(static_cast<const uint8_t *>(in), static_cast<uint8_t *>(out),
                                       L, out_capacity, d_out_nbytes, workspace, workspace_bytes, rp,
-                                      static_cast<hipStream_t>(stream)));
+                                      static_cast<hipStream_t>(stream), filter));
 }
 
 int bsg_compress_lz4(const void *in, void *out, int64_t n, int64_t elem_size, int64_t block_size,
@@ -217,6 +242,17 @@ int bsg_compress_lz4(const void *in, void *out, int64_t n, int64_t elem_size, in
     if (!make_layout(n, elem_size, block_size, &L)) return BSG_EINVAL;
     return compress_common(in, out, L, out_capacity, d_out_nbytes, workspace, workspace_bytes,
                            nullptr, stream);
+}
+
+int bsg_compress_lz4_filter(const void *in, void *out, int64_t n, int64_t elem_size,
+                            int64_t block_size, int32_t filter, int64_t out_capacity,
+                            int64_t *d_out_nbytes, void *workspace, int64_t workspace_bytes,
+                            void *stream)
+{
+    Layout L;
+    if (!make_layout(n, elem_size, block_size, &L)) return BSG_EINVAL;
+    return compress_common(in, out, L, out_capacity, d_out_nbytes, workspace, workspace_bytes,
+                           nullptr, stream, filter);
 }
 
 int bsg_round_compress_lz4(const void *vis_in, const float *autos, int64_t F, int64_t I,
@@ -235,9 +271,11 @@ int bsg_round_compress_lz4(const void *vis_in, const float *autos, int64_t F, in
                            workspace_bytes, &rp, stream);
 }
 
-int bsg_decompress_lz4(const void *in, int64_t in_nbytes, void *out, int64_t n, int64_t elem_size,
-                       int64_t block_size, int32_t *d_status, void *stream)
+static int decompress_common(const void *in, int64_t in_nbytes, void *out, int64_t n,
+                             int64_t elem_size, int64_t block_size, int32_t *d_status,
+                             void *stream, int filter)
 {
+    if (filter != BSG_FILTER_BIT && filter != BSG_FILTER_BYTE) return BSG_EINVAL;
     Layout L;
     if (!make_layout(n, elem_size, block_size, &L)) return BSG_EINVAL;
     if (L.block_bytes() > BSG_MAX_BLOCK_BYTES) return BSG_EINVAL;
@@ -246,7 +284,22 @@ int bsg_decompress_lz4(const void *in, int64_t in_nbytes, void *out, int64_t n, 
     if (in_nbytes < fixed_stream_bytes(L)) return BSG_ECORRUPT;
     return hip_status(launch_decompress(static_cast<const uint8_t *>(in), in_nbytes,
                                         static_cast<uint8_t *>(out), L, d_status,
-                                        static_cast<hipStream_t>(stream)));
+                                        static_cast<hipStream_t>(stream), filter));
+}
+
+int bsg_decompress_lz4(const void *in, int64_t in_nbytes, void *out, int64_t n, int64_t elem_size,
+                       int64_t block_size, int32_t *d_status, void *stream)
+{
+    return decompress_common(in, in_nbytes, out, n, elem_size, block_size, d_status, stream,
+                             BSG_FILTER_BIT);
+}
+
+int bsg_decompress_lz4_filter(const void *in, int64_t in_nbytes, void *out, int64_t n,
+                              int64_t elem_size, int64_t block_size, int32_t filter,
+                              int32_t *d_status, void *stream)
+{
+    return decompress_common(in, in_nbytes, out, n, elem_size, block_size, d_status, stream,
+                             filter);
 }
 
 int bsg_read_header(const void *host_bytes, int64_t nbytes, bsg_header *hdr)
@@ -254,7 +307,7 @@ int bsg_read_header(const void *host_bytes, int64_t nbytes, bsg_header *hdr)
     if (!host_bytes || !hdr) return BSG_EINVAL;
     if (nbytes < kHeaderBytes) return BSG_ECORRUPT;
     std::memcpy(hdr, host_bytes, sizeof(bsg_header));
-    if (hdr->magic != BSG_MAGIC) return BSG_ECORRUPT;
+    if (hdr->magic != BSG_MAGIC && hdr->magic != BSG_MAGIC_BYTE) return BSG_ECORRUPT;
     return BSG_OK;
 }
 

@@ -170,11 +170,13 @@ hipError_t launch_round_i32(const int32_t *vin, int32_t *vout, const RoundParams
 hipError_t launch_noise_comp(const float *vis, const RoundParams &rp, double *scale, hipStream_t s);
 hipError_t launch_shuffle(const uint8_t *in, uint8_t *out, const Layout &L, bool inverse,
                           hipStream_t s);
+hipError_t launch_byteshuffle(const uint8_t *in, uint8_t *out, const Layout &L, bool inverse,
+                              hipStream_t s);
 hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int64_t cap,
                            int64_t *d_nbytes, void *ws, int64_t ws_bytes,
-                           const RoundParams *rp, hipStream_t s);
+                           const RoundParams *rp, hipStream_t s, int filter = BSG_FILTER_BIT);
 int64_t compress_workspace(const Layout &L);
 hipError_t launch_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out,
-                             const Layout &L, int32_t *d_status, hipStream_t s);
+                             const Layout &L, int32_t *d_status, hipStream_t s, int filter = BSG_FILTER_BIT);
 
 } // namespace bsg

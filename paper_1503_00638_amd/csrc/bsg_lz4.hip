@@ -141,6 +141,7 @@ struct DecArgs {
     int64_t n, E, nb, n_full, last, n_blocks, tail;
     int32_t *status;
     int fast_out; // out is 16-byte aligned
+    uint32_t magic; // the stream's filter: bit transpose or byte shuffle
 };
 
 template <int MAXB, int EC>
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(64) void k_decode(DecArgs a)
     const int64_t payload_len = a.in_nbytes - table_end - tail_bytes; // >= 0 (host-checked)
     const uint8_t *payload = a.in + table_end;
     if (b == a.n_blocks) { // header check and raw tail
-        if (!header_ok(a.in, payload_len, a.n, a.E, a.nb, a.n_blocks)) {
+        if (!header_ok(a.in, payload_len, a.n, a.E, a.nb, a.n_blocks, a.magic)) {
             fail(a.status);
             return;
         }
@@ -187,6 +188,7 @@ hipError_t encode_dispatch(const EncArgs &ea, int64_t nblocks, const RoundParams
     if (rp) return ec == 4 ? encode_launch<MAXB, 4, true>(ea, nblocks, *rp, s)
                            : encode_launch<MAXB, 0, true>(ea, nblocks, *rp, s);
     switch (ec) {
+    case kByteShuffle: return encode_launch<MAXB, kByteShuffle, false>(ea, nblocks, none, s);
     case 1: return encode_launch<MAXB, 1, false>(ea, nblocks, none, s);
     case 2: return encode_launch<MAXB, 2, false>(ea, nblocks, none, s);
     case 4: return encode_launch<MAXB, 4, false>(ea, nblocks, none, s);
@@ -208,6 +210,7 @@ template <int MAXB>
 hipError_t decode_dispatch(const DecArgs &a, int ec, hipStream_t s)
 {
     switch (ec) {
+    case kByteShuffle: return decode_launch<MAXB, kByteShuffle>(a, s);
     case 1: return decode_launch<MAXB, 1>(a, s);
     case 2: return decode_launch<MAXB, 2>(a, s);
     case 4: return decode_launch<MAXB, 4>(a, s);
@@ -232,7 +235,7 @@ int64_t compress_workspace(const Layout &L)
 
 hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int64_t cap,
                            int64_t *d_nbytes, void *ws, int64_t ws_bytes, const RoundParams *rp,
-                           hipStream_t s)
+                           hipStream_t s, int filter)
 {
     (void)ws_bytes;
     const int64_t slot = (lz4_bound(L.block_bytes()) + 15) / 16 * 16;
@@ -246,13 +249,13 @@ hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int
 
     EncArgs ea{in, L.nb, L.E, L.n_full, L.last, slots, slot, sizes, 0};
     RoundParams none{};
-    const int ec = element_class(L.E);
+    const int ec = filter == BSG_FILTER_BYTE ? kByteShuffle : element_class(L.E);
     hipError_t e = L.block_bytes() <= kSmallBlock
                        ? encode_dispatch<kSmallBlock>(ea, L.n_blocks, rp, ec, s)
                        : encode_dispatch<kLargeBlock>(ea, L.n_blocks, rp, ec, s);
     if (e != hipSuccess) return e;
 
-    bsg_header hdr{BSG_MAGIC, (uint32_t)L.E, (uint64_t)L.n, (uint32_t)L.nb, (uint32_t)L.n_blocks};
+    bsg_header hdr{filter == BSG_FILTER_BYTE ? BSG_MAGIC_BYTE : BSG_MAGIC, (uint32_t)L.E, (uint64_t)L.n, (uint32_t)L.nb, (uint32_t)L.n_blocks};
     const int64_t fixed = kHeaderBytes + 8 * (L.n_blocks + 1) + L.tail * L.E;
     if (n_tiles > 0) {
         hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)n_tiles), dim3(256), 0, s, sizes, L.n_blocks,
@@ -275,11 +278,12 @@ hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int
 }
 
 hipError_t launch_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, const Layout &L,
-                             int32_t *d_status, hipStream_t s)
+                             int32_t *d_status, hipStream_t s, int filter)
 {
     DecArgs a{in,     in_nbytes,  out,    L.n,        L.E,    L.nb, L.n_full,
-              L.last, L.n_blocks, L.tail, d_status, ((uintptr_t)out % 16) == 0};
-    const int ec = element_class(L.E);
+              L.last, L.n_blocks, L.tail, d_status, ((uintptr_t)out % 16) == 0,
+              filter == BSG_FILTER_BYTE ? BSG_MAGIC_BYTE : BSG_MAGIC};
+    const int ec = filter == BSG_FILTER_BYTE ? kByteShuffle : element_class(L.E);
     return L.block_bytes() <= kSmallBlock ? decode_dispatch<kSmallBlock>(a, ec, s)
                                           : decode_dispatch<kLargeBlock>(a, ec, s);
 }

@@ -103,8 +103,45 @@ __device__ __forceinline__ void block_forward_ballot_round(const uint8_t *__rest
     }
 }
 
+// Element class of kernels that apply the byte shuffle instead of the bit
+// transpose (the Blosc-style filter the paper compares against in Section
+// 4.1 and Table t:performance): byte k of element i of a block goes to byte
+// k * elems + i.
+constexpr int kByteShuffle = -1;
+
+// Lanes take 4 elements at a time, so every LDS access is one aligned dword
+// (elems is a multiple of 8).
+__device__ __forceinline__ void block_forward_bytes(const uint8_t *__restrict__ in, uint8_t *lds,
+                                                    int64_t elems, int64_t E)
+{
+    uint32_t *l32 = reinterpret_cast<uint32_t *>(lds);
+    for (int64_t g = threadIdx.x; g < elems / 4; g += kWave) {
+        const uint8_t *src = in + 4 * g * E;
+        for (int64_t k = 0; k < E; ++k)
+            l32[(k * elems + 4 * g) >> 2] = (uint32_t)src[k] | ((uint32_t)src[E + k] << 8) |
+                                           ((uint32_t)src[2 * E + k] << 16) |
+                                           ((uint32_t)src[3 * E + k] << 24);
+    }
+}
+
+__device__ __forceinline__ void block_inverse_bytes(const uint8_t *lds, uint8_t *__restrict__ out,
+                                                    int64_t elems, int64_t E)
+{
+    const uint32_t *l32 = reinterpret_cast<const uint32_t *>(lds);
+    for (int64_t g = threadIdx.x; g < elems / 4; g += kWave) {
+        uint8_t *dst = out + 4 * g * E;
+        for (int64_t k = 0; k < E; ++k) {
+            const uint32_t v = l32[(k * elems + 4 * g) >> 2];
+            dst[k] = (uint8_t)v;
+            dst[E + k] = (uint8_t)(v >> 8);
+            dst[2 * E + k] = (uint8_t)(v >> 16);
+            dst[3 * E + k] = (uint8_t)(v >> 24);
+        }
+    }
+}
+
 // EC: the element size this kernel instance has a register fast path for
-// (1, 2, 4, 8, 12, 16), or 0 for the generic ballot path only.
+// (1, 2, 4, 8, 12, 16), 0 for the generic ballot path only, or kByteShuffle.
 template <int EC, bool ROUND>
 __device__ __forceinline__ void stage_block(const uint8_t *__restrict__ src, int64_t elems,
                                             int64_t E, uint8_t *lds, const RoundParams &rp,
@@ -116,6 +153,8 @@ __device__ __forceinline__ void stage_block(const uint8_t *__restrict__ src, int
             stage_fast<4, true>(src, elems, lds, rp, first_elem);
         else
             block_forward_ballot_round(src, lds, elems, rp, first_elem);
+    } else if constexpr (EC == kByteShuffle) {
+        block_forward_bytes(src, lds, elems, E);
     } else {
         if constexpr (EC != 0) {
             if (elems % Unit<EC>::G == 0 && ((uintptr_t)src % 16) == 0) {
@@ -546,7 +585,10 @@ template <int EC>
 __device__ __forceinline__ void unstage_block(const uint8_t *lds, int64_t elems, int64_t E,
                                               uint8_t *__restrict__ dst, bool fast_out)
 {
-    if constexpr (EC != 0) {
+    if constexpr (EC == kByteShuffle) {
+        block_inverse_bytes(lds, dst, elems, E);
+        return;
+    } else if constexpr (EC != 0) {
         if (fast_out && elems % Unit<EC>::G == 0) {
             unstage_fast<EC>(lds, elems, dst);
             return;
@@ -657,11 +699,12 @@ __device__ __forceinline__ bool decode_one(const uint8_t *__restrict__ payload, 
 // Header fields and offsets table ends of a stream agree with the expected
 // layout.  Called by one wavefront.
 __device__ __forceinline__ bool header_ok(const uint8_t *in, int64_t payload_len, int64_t n,
-                                          int64_t E, int64_t nb, int64_t n_blocks)
+                                          int64_t E, int64_t nb, int64_t n_blocks,
+                                          uint32_t magic = BSG_MAGIC)
 {
     const bsg_header *h = reinterpret_cast<const bsg_header *>(in);
     const uint64_t *off = reinterpret_cast<const uint64_t *>(in + kHeaderBytes);
-    return h->magic == BSG_MAGIC && h->elem_size == (uint32_t)E && h->n == (uint64_t)n &&
+    return h->magic == magic && h->elem_size == (uint32_t)E && h->n == (uint64_t)n &&
            h->block_elems == (uint32_t)nb && h->n_blocks == (uint32_t)n_blocks && off[0] == 0 &&
            off[n_blocks] == (uint64_t)payload_len;
 }

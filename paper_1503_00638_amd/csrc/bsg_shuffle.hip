@@ -88,6 +88,68 @@ hipError_t blocks_launch(const uint8_t *in, uint8_t *out, int64_t nblocks, int64
 
 } // namespace
 
+namespace {
+
+// Byte shuffle of whole blocks, one thread per output dword: forward, output
+// byte k * nb + i of a block is input byte i * E + k; inverse, output byte
+// i * E + k is input byte k * nb + i.  Block bytes are a multiple of 8, so
+// dwords never straddle blocks.
+template <bool INV>
+__global__ __launch_bounds__(256) void k_byteshuffle(const uint8_t *__restrict__ in,
+                                                     uint8_t *__restrict__ out, int64_t n_blocks,
+                                                     int64_t nb, int64_t E)
+{
+    const int64_t words_per_block = nb * E / 4;
+    const int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (d >= n_blocks * words_per_block) return;
+    const int64_t b = d / words_per_block, w = d - b * words_per_block;
+    const uint8_t *src = in + b * nb * E;
+    uint32_t v = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t o = 4 * w + q; // output byte within the block
+        int64_t i, k;
+        if (INV) {
+            i = o / E;
+            k = o - i * E;
+        } else {
+            k = o / nb;
+            i = o - k * nb;
+        }
+        v |= (uint32_t)src[INV ? k * nb + i : i * E + k] << (8 * q);
+    }
+    reinterpret_cast<uint32_t *>(out + b * nb * E)[w] = v;
+}
+
+template <bool INV>
+hipError_t bytes_launch(const uint8_t *in, uint8_t *out, int64_t n_blocks, int64_t nb, int64_t E,
+                        hipStream_t s)
+{
+    const int64_t words = n_blocks * nb * E / 4;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_byteshuffle<INV>), dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,
+                       in, out, n_blocks, nb, E);
+    return hipGetLastError();
+}
+
+} // namespace
+
+hipError_t launch_byteshuffle(const uint8_t *in, uint8_t *out, const Layout &L, bool inverse,
+                              hipStream_t s)
+{
+    hipError_t e = inverse ? bytes_launch<true>(in, out, L.n_full, L.nb, L.E, s)
+                           : bytes_launch<false>(in, out, L.n_full, L.nb, L.E, s);
+    const int64_t off = L.n_full * L.nb * L.E;
+    if (e == hipSuccess && L.last)
+        e = inverse ? bytes_launch<true>(in + off, out + off, 1, L.last, L.E, s)
+                    : bytes_launch<false>(in + off, out + off, 1, L.last, L.E, s);
+    if (e == hipSuccess && L.tail) {
+        const int64_t t0 = (L.n - L.tail) * L.E;
+        hipLaunchKernelGGL(k_copy_bytes, dim3(1), dim3(64), 0, s, in + t0, out + t0, L.tail * L.E);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
 hipError_t launch_shuffle(const uint8_t *in, uint8_t *out, const Layout &L, bool inverse,
                           hipStream_t s)
 {

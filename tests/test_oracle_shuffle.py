@@ -147,3 +147,49 @@ def test_default_and_invalid_block(oracle_lib):
     assert oracle_lib.block_elems(0, 8) < 0
     with pytest.raises(Exception):
         oracle_lib.bitshuffle(np.zeros(64, np.uint8), 4, 12)
+
+
+# ---- the comparison filter: Blosc-style byte shuffle (Section 4.1) -----------
+import oracle  # noqa: E402
+@pytest.mark.parametrize("E,nb,n", [(1, 64, 64), (2, 8, 101), (4, 2048, 2048 * 3 + 13), (8, 16, 16),
+                                    (3, 24, 77), (16, 8, 8 * 5 + 7), (4, 8, 3)])
+def test_byteshuffle_numpy_reduction_and_round_trip(E, nb, n):
+    rng = np.random.default_rng(E * 7 + nb + n)
+    x = rng.integers(0, 256, n * E, dtype=np.uint8)
+    y = oracle.byteshuffle(x, E, nb)
+    full, rem = divmod(n, nb)
+    last = rem - rem % 8
+    for b in range(full + (1 if last else 0)):
+        elems = nb if b < full else last
+        blk = x[b * nb * E:(b * nb + elems) * E]
+        assert np.array_equal(y[b * nb * E:(b * nb + elems) * E], blk.reshape(elems, E).T.reshape(-1))
+    tail0 = (n - rem % 8) * E
+    assert np.array_equal(y[tail0:], x[tail0:])
+    assert np.array_equal(oracle.byteunshuffle(y, E, nb), x)
+
+
+def test_byte_filter_streams():
+    import lz4ref
+    vis, autos = synth.gen_vis(16, 8, 64, 0)
+    r = oracle.round_to_noise(vis, autos, 3.9e6, 0.01)
+    data = r.view(np.uint8).reshape(-1)
+    sb = oracle.compress(data, 4, 2048, filter=1)
+    s0 = oracle.compress(data, 4, 2048)
+    assert sb[:4].tobytes() == b"BSB1" and s0[:4].tobytes() == b"BSG1"
+    assert np.array_equal(oracle.decompress(sb, data.size // 4, 4, 2048, filter=1), data)
+    with pytest.raises(oracle.OracleError):
+        oracle.decompress(sb, data.size // 4, 4, 2048, filter=0)
+    with pytest.raises(oracle.OracleError):
+        oracle.decompress(s0, data.size // 4, 4, 2048, filter=1)
+    # the payload blocks are standard LZ4 blocks of the byte-shuffled block
+    if lz4ref.available():
+        nblk = int(np.frombuffer(sb[20:24].tobytes(), np.uint32)[0])
+        off = np.frombuffer(sb[24:24 + 8 * (nblk + 1)].tobytes(), np.uint64)
+        pay = sb[24 + 8 * (nblk + 1):]
+        shuffled = oracle.byteshuffle(data, 4, 2048)
+        for b in range(nblk):
+            blk = lz4ref.decompress_safe(pay[off[b]:off[b + 1]].tobytes(), 8192)
+            assert blk == shuffled[b * 8192:(b + 1) * 8192].tobytes()
+    # the comparison the paper makes: the bit transpose compresses noise-
+    # dominated data far better than the byte shuffle
+    assert s0.size < 0.75 * sb.size
