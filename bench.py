@@ -88,7 +88,7 @@ def main(argv=None):
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale)")
-    ap.add_argument("--workload", choices=("chunk", "batch", "serve", "sweep", "filters"),
+    ap.add_argument("--workload", choices=("chunk", "batch", "serve", "sweep", "filters", "extensions"),
                     default="chunk",
                     help="chunk: one 2.16 GB CHIME-shaped chunk (default); batch: 4096 "
                          "independent chunks; serve: Poisson request stream; sweep: bit "
@@ -117,6 +117,8 @@ def main(argv=None):
         return bench_sweep(args, torch, bsg)
     if args.workload == "filters":
         return bench_filters(args, torch, bsg)
+    if args.workload == "extensions":
+        return bench_extensions(args, torch, bsg)
 
     w = WORKLOAD
     dev = torch.device("cuda:0")
@@ -499,6 +501,105 @@ def bench_filters(args, torch, bsg):
         "filters": rows,
         "paper_ratios_for_context": {"bitshuffle_lz4": 0.279, "blosc_lz4": 0.473},
         "source_digest": source_digest(),
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def bench_extensions(args, torch, bsg):
+    """The rows beyond the float path, on the CHIME-Pathfinder shape (1024
+    freq, 8256 products, 32 times): integer visibilities (int32 re/im, the
+    correlator's own type) rounded and compressed as 8-byte elements, and
+    the compensation of the diagonal noise model (factor, then rounding
+    with it) on point-source-dominated visibilities."""
+    from paper_1503_00638_amd import synth
+
+    w = WORKLOAD
+    dev = torch.device("cuda:0")
+    F, I, T = w["F"], w["I"], w["T"]
+    res_rows = {}
+    # integer visibilities: the float model scaled by 1024 and rounded
+    vis, autos = synth.gen_vis_device(F, I, T, w["seed"], w["N"], device=dev)
+    vi = torch.round(torch.view_as_real(vis) * 1024.0).to(torch.int32)
+    pairs = torch.from_numpy(synth.product_pairs(I)).to(dev)
+    ai = vi[..., 0][:, pairs[:, 0] == pairs[:, 1], :].contiguous()
+    del vis, autos
+    U = vi.numel() * 4
+    ro = torch.empty_like(vi)
+    t_round = float(np.median(_time_calls(
+        torch, lambda: bsg.round_to_noise_i32(vi, ai, w["N"], w["f"], out=ro), args.steps,
+        args.warmup)))
+    flat = ro.view(torch.uint8).reshape(-1)
+    n8, nb8 = U // 8, w["block_bytes"] // 8
+    out = torch.empty(bsg.compress_bound(n8, 8, nb8), dtype=torch.uint8, device=dev)
+    ws = torch.empty(bsg.workspace_size(n8, 8, nb8), dtype=torch.uint8, device=dev)
+    nbytes = torch.empty(1, dtype=torch.int64, device=dev)
+    t_comp = float(np.median(_time_calls(
+        torch, lambda: bsg.compress(flat, 8, nb8, out=out, workspace=ws, nbytes=nbytes), args.steps,
+        args.warmup)))
+    m = int(nbytes.item())
+    dec = torch.empty(U, dtype=torch.uint8, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    t_dec = float(np.median(_time_calls(
+        torch, lambda: bsg.decompress(out, m, n8, 8, nb8, out=dec, status=st), args.steps,
+        args.warmup)))
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and torch.equal(dec, flat)
+    res_rows["integer_visibilities"] = {
+        "round_GBps": round(U / (t_round * 1e-3) / 1e9, 2),
+        "round_hbm_frac": round((2 * U + ai.numel() * 4) / (t_round * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "compress_e8_GBps": round(U / (t_comp * 1e-3) / 1e9, 2),
+        "decompress_e8_GBps": round(U / (t_dec * 1e-3) / 1e9, 2), "ratio": round(m / U, 5)}
+    del vi, ai, ro, flat, out, ws, dec
+    # compensation: a source adding 40 % of the receiver power to every product
+    vis, autos = synth.gen_vis_device(F, I, T, w["seed"], w["N"], device=dev)
+    vr = torch.view_as_real(vis)
+    vr[..., 0] += 400.0
+    autos += 400.0
+    U = vis.numel() * 8
+    scale = torch.empty((F, T), dtype=torch.float64, device=dev)
+    t_fac = float(np.median(_time_calls(
+        torch, lambda: bsg.noise_compensation(vis, autos, out=scale), args.steps, args.warmup)))
+    rout = torch.empty_like(vis)
+    t_rs = float(np.median(_time_calls(
+        torch, lambda: bsg.round_to_noise_scaled(vis, autos, w["N"], w["f"], scale, out=rout),
+        args.steps, args.warmup)))
+    res_rows["noise_compensation"] = {
+        "factor_GBps": round(U / (t_fac * 1e-3) / 1e9, 2),
+        "factor_hbm_frac": round((U + autos.numel() * 4) / (t_fac * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "factor_min": round(float(scale.min().item()), 6),
+        "scaled_round_GBps": round(U / (t_rs * 1e-3) / 1e9, 2)}
+    del vis, autos, vr, rout, scale
+    # full-covariance noise for small arrays: per sample a D x D covariance,
+    # D = I^2, factorised and inverted in LDS (2 D^3 / 3 flops for the
+    # Cholesky factor and the triangular inverse, D^2 for the diagonal)
+    fc = {}
+    for Ic, Fc, Tc in ((8, 1024, 64), (11, 256, 64)):
+        vis, autos = synth.gen_vis_device(Fc, Ic, Tc, w["seed"], w["N"], device=dev)
+        out_fc = torch.empty_like(vis)
+        t_fc = float(np.median(_time_calls(
+            torch, lambda: bsg.round_to_noise_fullcov(vis, autos, w["N"], w["f"], out=out_fc),
+            args.steps, args.warmup)))
+        D = Ic * Ic
+        samples = Fc * Tc
+        fc[f"I{Ic}"] = {"samples": samples, "dof_per_sample": D, "ms": round(t_fc, 3),
+                        "samples_per_s": round(samples / (t_fc * 1e-3), 1),
+                        "GBps": round(vis.numel() * 8 / (t_fc * 1e-3) / 1e9, 2),
+                        "fp64_TFLOPs": round(samples * (2 * D ** 3 / 3) / (t_fc * 1e-3) / 1e12, 3)}
+        del vis, autos, out_fc
+    res_rows["full_covariance"] = fc
+    res = {
+        "metric": "uncompressed GB/s (compress & decompress) + % HBM peak; p50/p99 latency",
+        "value": res_rows["integer_visibilities"]["round_GBps"], "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i32/f64", "data": "synthetic",
+        "config": {"workload": "integer visibilities and noise-model compensation on the "
+                               "CHIME-Pathfinder shape (1024 freq, 8256 products, 32 times), "
+                               "f=0.01, N=3.9e6, 8192-byte blocks; full-covariance rounding "
+                               "for small arrays (8 inputs x 1024 freq x 64 times, 11 inputs x "
+                               "256 freq x 64 times)",
+                   "parallelism": "single GPU"},
+        "rows": res_rows, "source_digest": source_digest(),
     }
     print(json.dumps(res), flush=True)
     return 0

@@ -87,8 +87,8 @@ int64_t bsg_block_elems(int64_t elem_size, int64_t block_size);
  *   c = (12 f) / (2 N) in IEEE double (the product of two floats is exact);
  *   k = the largest integer with 4^k < G2; re and im are rounded to the
  *   nearest multiple of 2^k, ties to even; the imaginary part of an auto is
- *   copied.  G2 not positive and finite (f = 0, a zero, negative or NaN auto)
- *   leaves the element unchanged; NaN and Inf values pass through; the sign
+ *   copied.  G2 not positive and finite (f = 0, a zero or NaN auto, autos
+ *   of opposite sign) leaves the element unchanged; NaN and Inf values pass through; the sign
  *   of zero is kept.
  * Errors: BSG_EINVAL for negative sizes, NULL pointers with a non-empty
  *   array, n_samples <= 0 or f < 0 or non-finite; BSG_EHIP on launch failure.
@@ -118,6 +118,27 @@ int bsg_noise_compensation(const void *vis, const float *autos, int64_t F, int64
 int bsg_round_to_noise_scaled(const void *vis_in, void *vis_out, const float *autos, int64_t F,
                               int64_t I, int64_t T, const int32_t *prod_map, double n_samples,
                               double f, const double *scale, void *stream);
+
+/* Full-covariance noise for small arrays (Section 3.1, Eqs. rad_full1-3 and
+ * Eq. noise; I <= 11 inputs).  Per (frequency, time) the covariance C of
+ * the I^2 real degrees of freedom (in product order: Re of each product,
+ * then Im if it is a cross product) is built from the sample's visibilities
+ * (V_ab = conj(V_ba), V_aa = the measured auto), and each degree of freedom
+ * gets the noise s_k^2 = 1 / (C^-1)_kk (not marginalised over the others).
+ * With Q = 2N C, (Q^-1)_kk is computed from the Cholesky factor of Q and
+ * its inverse with every sum in increasing index order.
+ * bsg_fullcov_inverse_diag: qdiag = device float64 [F][T][I^2] receives
+ *   (Q^-1)_kk, or NaN for every k of a sample whose Q is not positive
+ *   definite.
+ * bsg_round_to_noise_fullcov: rounding of Section 3.2 with G2 = c /
+ *   (Q^-1)_kk, c = (12 f) / (2N), each degree of freedom with its own k;
+ *   samples without an estimate are left unchanged; Im of autos copied;
+ *   vis_out may equal vis_in.  Default product order only.
+ * Layouts and errors as bsg_round_to_noise (BSG_EINVAL also for I > 11). */
+int bsg_fullcov_inverse_diag(const void *vis, const float *autos, int64_t F, int64_t I,
+                             int64_t T, double *qdiag, void *stream);
+int bsg_round_to_noise_fullcov(const void *vis_in, void *vis_out, const float *autos, int64_t F,
+                               int64_t I, int64_t T, double n_samples, double f, void *stream);
 
 /* Integer visibilities, the correlator's own data type (Section 5): the
  * same noise-relative rounding on int32 values.

@@ -78,6 +78,10 @@ def lib():
         L.oracle_compress_filter.restype = i64
         L.oracle_decompress_filter.argtypes = [vp, i64, vp, i64, i64, i64, i32, i32]
         L.oracle_decompress_filter.restype = i64
+        L.oracle_fullcov_inverse_diag.argtypes = [vp, vp, i64, i64, i64, vp]
+        L.oracle_fullcov_inverse_diag.restype = i32
+        L.oracle_round_to_noise_fullcov.argtypes = [vp, vp, vp, i64, i64, i64, dbl, dbl]
+        L.oracle_round_to_noise_fullcov.restype = i32
         L.oracle_max_threads.argtypes = []
         L.oracle_max_threads.restype = i32
         _lib = L
@@ -159,6 +163,33 @@ def round_to_noise_scaled(vis: np.ndarray, autos: np.ndarray, n_samples: float, 
                                             float(n_samples), float(f), _ptr(scale), int(nthreads))
     if rc != 0:
         raise OracleError(rc, "round_to_noise_scaled")
+    return out
+
+
+def fullcov_inverse_diag(vis: np.ndarray, autos: np.ndarray) -> np.ndarray:
+    """(F, T, I^2) float64: (Q^-1)_kk per degree of freedom, Q = 2N C."""
+    vis = np.ascontiguousarray(vis, dtype=np.complex64)
+    autos = np.ascontiguousarray(autos, dtype=np.float32)
+    F, I, T = autos.shape
+    if vis.shape != (F, I * (I + 1) // 2, T):
+        raise ValueError("shape mismatch")
+    out = np.empty((F, T, I * I), dtype=np.float64)
+    rc = lib().oracle_fullcov_inverse_diag(_ptr(vis), _ptr(autos), F, I, T, _ptr(out))
+    if rc != 0:
+        raise OracleError(rc, "fullcov_inverse_diag")
+    return out
+
+
+def round_to_noise_fullcov(vis: np.ndarray, autos: np.ndarray, n_samples: float,
+                           f: float) -> np.ndarray:
+    vis = np.ascontiguousarray(vis, dtype=np.complex64)
+    autos = np.ascontiguousarray(autos, dtype=np.float32)
+    F, I, T = autos.shape
+    out = np.empty_like(vis)
+    rc = lib().oracle_round_to_noise_fullcov(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
+                                             float(n_samples), float(f))
+    if rc != 0:
+        raise OracleError(rc, "round_to_noise_fullcov")
     return out
 
 

@@ -265,6 +265,199 @@ int oracle_round_to_noise_scaled(const float *vis_in, float *vis_out, const floa
 }
 
 /* ----------------------------------------------------------------------
+ * Full-covariance noise for small arrays (Section 3.1, Eqs. rad_full1-3 and
+ * Eq. noise).  Per (frequency, time) the real degrees of freedom are, in
+ * product order, Re of every product and Im of every cross product (the Im
+ * of an auto is identically zero and carries no noise): D = I^2 of them.
+ * With V_ab = conj(V_ba) and V_aa = the measured auto, 2N times the
+ * covariance between (x, ij) and (y, gh) is
+ *   Re Re:  Re[V_ig conj(V_jh) + V_ih conj(V_jg)]
+ *   Im Im:  Re[V_ig conj(V_jh) - V_ih conj(V_jg)]
+ *   Re Im:  Im[-V_ig conj(V_jh) + V_ih conj(V_jg)]     (Im Re by symmetry)
+ * and the noise of a degree of freedom k is s_k^2 = 1 / (C^-1)_kk, the
+ * variance not marginalised over the others.  With Q = 2N C,
+ * G2 = 12 f s_k^2 = c / (Q^-1)_kk, c = (12 f) / (2N) as in the diagonal case.
+ * (Q^-1)_kk comes from the Cholesky factor Q = L L^T and M = L^-1:
+ * (Q^-1)_kk = sum over i >= k of M_ik^2.  Every sum runs in increasing
+ * index order.  A (frequency, time) whose Q is not positive definite (a
+ * pivot not > 0, NaN data) is left unchanged.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double re, im;
+} cplx;
+
+static cplx cmul_conj(cplx a, cplx b) /* a * conj(b) */
+{
+    cplx r = {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+    return r;
+}
+
+int oracle_fullcov_inverse_diag(const float *vis, const float *autos, int64_t F, int64_t I,
+                                int64_t T, double *qdiag)
+{
+    if (F < 0 || I < 0 || T < 0 || I > 64)
+        return -1;
+    const int64_t P = I * (I + 1) / 2, D = I * I;
+    if (F * T * D > 0 && (!vis || !autos || !qdiag))
+        return -1;
+    /* degree of freedom k -> (product p, 0 = Re / 1 = Im), and product -> (i, j) */
+    int64_t *dof_p = (int64_t *)malloc((size_t)(D > 0 ? D : 1) * sizeof(int64_t));
+    int *dof_im = (int *)malloc((size_t)(D > 0 ? D : 1) * sizeof(int));
+    int64_t *pi = (int64_t *)malloc((size_t)(P > 0 ? P : 1) * sizeof(int64_t));
+    int64_t *pj = (int64_t *)malloc((size_t)(P > 0 ? P : 1) * sizeof(int64_t));
+    int64_t *pidx = (int64_t *)malloc((size_t)(I > 0 ? I * I : 1) * sizeof(int64_t));
+    double *Q = (double *)malloc((size_t)(D > 0 ? D * D : 1) * sizeof(double));
+    double *M = (double *)malloc((size_t)(D > 0 ? D * D : 1) * sizeof(double));
+    cplx *V = (cplx *)malloc((size_t)(I > 0 ? I * I : 1) * sizeof(cplx));
+    if (!dof_p || !dof_im || !pi || !pj || !pidx || !Q || !M || !V) {
+        free(dof_p); free(dof_im); free(pi); free(pj); free(pidx); free(Q); free(M); free(V);
+        return -1;
+    }
+    {
+        int64_t p = 0, k = 0;
+        for (int64_t i = 0; i < I; i++)
+            for (int64_t j = i; j < I; j++) {
+                pi[p] = i;
+                pj[p] = j;
+                pidx[i * I + j] = p;
+                p++;
+            }
+        for (p = 0; p < P; p++) {
+            dof_p[k] = p;
+            dof_im[k] = 0;
+            k++;
+            if (pi[p] != pj[p]) {
+                dof_p[k] = p;
+                dof_im[k] = 1;
+                k++;
+            }
+        }
+    }
+    for (int64_t fr = 0; fr < F; fr++)
+        for (int64_t t = 0; t < T; t++) {
+            /* the Hermitian matrix V of this sample */
+            for (int64_t a = 0; a < I; a++)
+                for (int64_t b = 0; b < I; b++) {
+                    cplx v;
+                    if (a == b) {
+                        v.re = autos[(fr * I + a) * T + t];
+                        v.im = 0.0;
+                    } else {
+                        const int64_t lo = a < b ? a : b, hi = a < b ? b : a;
+                        const int64_t e = 2 * ((fr * P + pidx[lo * I + hi]) * T + t);
+                        v.re = vis[e];
+                        v.im = a < b ? (double)vis[e + 1] : -(double)vis[e + 1];
+                    }
+                    V[a * I + b] = v;
+                }
+            /* Q = 2N C */
+            for (int64_t x = 0; x < D; x++)
+                for (int64_t y = 0; y < D; y++) {
+                    const int64_t i = pi[dof_p[x]], j = pj[dof_p[x]];
+                    const int64_t g = pi[dof_p[y]], h = pj[dof_p[y]];
+                    const cplx A = cmul_conj(V[i * I + g], V[j * I + h]);
+                    const cplx B = cmul_conj(V[i * I + h], V[j * I + g]);
+                    double q;
+                    if (!dof_im[x] && !dof_im[y])
+                        q = A.re + B.re;
+                    else if (dof_im[x] && dof_im[y])
+                        q = A.re - B.re;
+                    else if (!dof_im[x]) /* Re ij, Im gh */
+                        q = -A.im + B.im;
+                    else { /* Im ij, Re gh = Re gh, Im ij */
+                        const cplx A2 = cmul_conj(V[g * I + i], V[h * I + j]);
+                        const cplx B2 = cmul_conj(V[g * I + j], V[h * I + i]);
+                        q = -A2.im + B2.im;
+                    }
+                    Q[x * D + y] = q;
+                }
+            /* Cholesky, right-looking: after step k the trailing block holds
+             * Q_ij - sum_{m <= k} L_im L_jm, subtracted in increasing m */
+            int ok = 1;
+            for (int64_t k = 0; k < D && ok; k++) {
+                const double d = Q[k * D + k];
+                if (!(d > 0.0) || isinf(d)) {
+                    ok = 0;
+                    break;
+                }
+                const double lkk = sqrt(d);
+                Q[k * D + k] = lkk;
+                for (int64_t i = k + 1; i < D; i++)
+                    Q[i * D + k] = Q[i * D + k] / lkk;
+                for (int64_t i = k + 1; i < D; i++)
+                    for (int64_t j = k + 1; j <= i; j++)
+                        Q[i * D + j] = Q[i * D + j] - Q[i * D + k] * Q[j * D + k];
+            }
+            double *out = qdiag + (fr * T + t) * D;
+            if (!ok) {
+                for (int64_t k = 0; k < D; k++)
+                    out[k] = NAN; /* no valid noise estimate */
+                continue;
+            }
+            /* M = L^-1 column by column: M_jj = 1 / L_jj, and for i > j
+             * M_ij = -(sum_{m=j}^{i-1} L_im M_mj) / L_ii */
+            for (int64_t j = 0; j < D; j++) {
+                M[j * D + j] = 1.0 / Q[j * D + j];
+                for (int64_t i = j + 1; i < D; i++) {
+                    double acc = Q[i * D + j] * M[j * D + j];
+                    for (int64_t m = j + 1; m < i; m++)
+                        acc = acc + Q[i * D + m] * M[m * D + j];
+                    M[i * D + j] = -acc / Q[i * D + i];
+                }
+                double q = 0.0;
+                for (int64_t i = j; i < D; i++)
+                    q = q + M[i * D + j] * M[i * D + j];
+                out[j] = q;
+            }
+        }
+    free(dof_p); free(dof_im); free(pi); free(pj); free(pidx); free(Q); free(M); free(V);
+    return 0;
+}
+
+int oracle_round_to_noise_fullcov(const float *vis_in, float *vis_out, const float *autos,
+                                  int64_t F, int64_t I, int64_t T, double n_samples, double f)
+{
+    if (!(n_samples > 0.0) || isinf(n_samples) || !(f >= 0.0) || isinf(f))
+        return -1;
+    if (F < 0 || I < 0 || T < 0 || I > 64)
+        return -1;
+    const int64_t P = I * (I + 1) / 2, D = I * I;
+    if (F * P * T == 0)
+        return 0;
+    if (!vis_in || !vis_out || !autos)
+        return -1;
+    double *qd = (double *)malloc((size_t)(F * T * D) * sizeof(double));
+    if (!qd)
+        return -1;
+    if (oracle_fullcov_inverse_diag(vis_in, autos, F, I, T, qd)) {
+        free(qd);
+        return -1;
+    }
+    const double c = (12.0 * f) / (2.0 * n_samples);
+    for (int64_t fr = 0; fr < F; fr++)
+        for (int64_t t = 0; t < T; t++) {
+            const double *q = qd + (fr * T + t) * D;
+            int64_t k = 0;
+            for (int64_t i = 0; i < I; i++)
+                for (int64_t j = i; j < I; j++) {
+                    const int64_t prod = (i * I - i * (i - 1) / 2) + (j - i);
+                    const int64_t e = 2 * ((fr * P + prod) * T + t);
+                    /* Re: G2 = c / (Q^-1)_kk; NaN (no estimate) leaves it */
+                    vis_out[e] = round_to_noise_1(vis_in[e], c / q[k]);
+                    k++;
+                    if (i != j) {
+                        vis_out[e + 1] = round_to_noise_1(vis_in[e + 1], c / q[k]);
+                        k++;
+                    } else {
+                        vis_out[e + 1] = vis_in[e + 1];
+                    }
+                }
+        }
+    free(qd);
+    return 0;
+}
+
+/* ----------------------------------------------------------------------
  * Integer visibilities (the data type of the paper's own evaluation,
  * Section 5): re and im are int32.  Every integer is already a multiple of
  * g = 1, so only k >= 1 changes anything (g <= 1 means no rounding).

@@ -51,6 +51,20 @@ int oracle_round_to_noise_scaled(const float *vis_in, float *vis_out, const floa
                                  int64_t F, int64_t I, int64_t T, const int32_t *prod_map,
                                  double n_samples, double f, const double *scale, int nthreads);
 
+/* Full-covariance noise for small arrays (Section 3.1, Eqs. rad_full1-3,
+ * Eq. noise; I <= 64).  Per (frequency, time), the I^2 real degrees of
+ * freedom in product order (Re of each product, then Im if it is a cross
+ * product); qdiag[F][T][I^2] receives (Q^-1)_kk with Q = 2N C from a
+ * Cholesky factor and its inverse, every sum in increasing index order, or
+ * NaN for the whole sample when Q is not positive definite. */
+int oracle_fullcov_inverse_diag(const float *vis, const float *autos, int64_t F, int64_t I,
+                                int64_t T, double *qdiag);
+/* Rounding with G2 = c / (Q^-1)_kk for each degree of freedom (c =
+ * (12 f) / (2N)); a sample without a valid estimate is left unchanged; Im
+ * of autos is copied.  Default product order only. */
+int oracle_round_to_noise_fullcov(const float *vis_in, float *vis_out, const float *autos,
+                                  int64_t F, int64_t I, int64_t T, double n_samples, double f);
+
 /* Integer visibilities (Section 5 data type): int32 [F][P][T][2] and int32
  * autos [F][I][T]; G2 from the exact int64 product rounded once to double;
  * rounding to a multiple of 2^k only for k >= 1, ties to even in integer

@@ -18,7 +18,8 @@ from ._lib import (BSG_ECAPACITY, BSG_ECORRUPT, BSG_EHIP, BSG_EINVAL, BSG_FILTER
                    BSG_FILTER_BYTE, BSG_OK, BsgError, Header)
 
 __all__ = [
-    "round_to_noise", "round_to_noise_i32", "noise_compensation", "round_to_noise_scaled", "bitshuffle", "bitunshuffle", "compress_bound", "workspace_size",
+    "round_to_noise", "round_to_noise_i32", "noise_compensation", "round_to_noise_scaled",
+    "fullcov_inverse_diag", "round_to_noise_fullcov", "bitshuffle", "bitunshuffle", "compress_bound", "workspace_size",
     "compress", "round_compress", "decompress", "block_elems", "read_header", "BsgError",
     "compress_sync", "decompress_sync", "BSG_OK", "BSG_EINVAL", "BSG_ECAPACITY",
     "BSG_ECORRUPT", "BSG_EHIP", "load", "BatchPlan", "byteshuffle", "byteunshuffle",
@@ -118,6 +119,33 @@ def round_to_noise_scaled(vis: torch.Tensor, autos: torch.Tensor, n_samples: flo
                                                      _ptr(prod_map), float(n_samples), float(f),
                                                      _ptr(scale), _stream_ptr(stream)),
                "round_to_noise_scaled")
+    return out
+
+
+def fullcov_inverse_diag(vis: torch.Tensor, autos: torch.Tensor, out: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+    """(Q^-1)_kk per sample and degree of freedom (float64 (F, T, I^2)),
+    Q = 2N C of Eqs. rad_full1-3 (I <= 11)."""
+    _require_device(vis, autos, out)
+    F, I, T = _vis_autos(vis, autos)
+    if out is None:
+        out = torch.empty((F, T, I * I), dtype=torch.float64, device=vis.device)
+    _lib.check(_lib.lib().bsg_fullcov_inverse_diag(_ptr(vis), _ptr(autos), F, I, T, _ptr(out),
+                                                    _stream_ptr(stream)), "fullcov_inverse_diag")
+    return out
+
+
+def round_to_noise_fullcov(vis: torch.Tensor, autos: torch.Tensor, n_samples: float, f: float,
+                           out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Rounding with the full-covariance noise of each degree of freedom."""
+    _require_device(vis, autos, out)
+    F, I, T = _vis_autos(vis, autos)
+    if out is None:
+        out = torch.empty_like(vis)
+    _lib.check(_lib.lib().bsg_round_to_noise_fullcov(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
+                                                      float(n_samples), float(f),
+                                                      _stream_ptr(stream)),
+               "round_to_noise_fullcov")
     return out
 
 

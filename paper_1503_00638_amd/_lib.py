@@ -27,6 +27,7 @@ EXPORTS = (
     "bsg_batch_compress", "bsg_batch_decompress", "bsg_round_to_noise_i32",
     "bsg_noise_compensation", "bsg_round_to_noise_scaled", "bsg_byteshuffle",
     "bsg_byteunshuffle", "bsg_compress_lz4_filter", "bsg_decompress_lz4_filter",
+    "bsg_fullcov_inverse_diag", "bsg_round_to_noise_fullcov",
 )
 
 
@@ -74,6 +75,10 @@ def _lib():
         L.bsg_noise_compensation.restype = i32
         L.bsg_round_to_noise_scaled.argtypes = [vp, vp, vp, i64, i64, i64, vp, dbl, dbl, vp, vp]
         L.bsg_round_to_noise_scaled.restype = i32
+        L.bsg_fullcov_inverse_diag.argtypes = [vp, vp, i64, i64, i64, vp, vp]
+        L.bsg_fullcov_inverse_diag.restype = i32
+        L.bsg_round_to_noise_fullcov.argtypes = [vp, vp, vp, i64, i64, i64, dbl, dbl, vp]
+        L.bsg_round_to_noise_fullcov.restype = i32
         for f in (L.bsg_bitshuffle, L.bsg_bitunshuffle, L.bsg_byteshuffle, L.bsg_byteunshuffle):
             f.argtypes = [vp, vp, i64, i64, i64, vp]
             f.restype = i32

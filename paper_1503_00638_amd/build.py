@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libbsg.so")
-SOURCES = ["bsg_api.hip", "bsg_round.hip", "bsg_shuffle.hip", "bsg_lz4.hip", "bsg_batch.hip"]
+SOURCES = ["bsg_api.hip", "bsg_round.hip", "bsg_shuffle.hip", "bsg_lz4.hip", "bsg_batch.hip",
+           "bsg_fullcov.hip"]
 OBJDIR = os.path.join(PKG, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -137,6 +137,32 @@ int bsg_round_to_noise_scaled(const void *vis_in, void *vis_out, const float *au
                                    rp, static_cast<hipStream_t>(stream)));
 }
 
+int bsg_fullcov_inverse_diag(const void *vis, const float *autos, int64_t F, int64_t I,
+                             int64_t T, double *qdiag, void *stream)
+{
+    if (F < 0 || I < 0 || T < 0 || I > fullcov_max_inputs()) return BSG_EINVAL;
+    if (F * T * I == 0) return BSG_OK;
+    if (!vis || !autos || !qdiag || (uintptr_t)vis % 8 || (uintptr_t)autos % 4 ||
+        (uintptr_t)qdiag % 8 || F * T > (int64_t)INT32_MAX)
+        return BSG_EINVAL;
+    return hip_status(launch_fullcov(static_cast<const float *>(vis), autos, F, I, T, 0.0, nullptr,
+                                     qdiag, static_cast<hipStream_t>(stream)));
+}
+
+int bsg_round_to_noise_fullcov(const void *vis_in, void *vis_out, const float *autos, int64_t F,
+                               int64_t I, int64_t T, double n_samples, double f, void *stream)
+{
+    if (!round_args_ok(F, I, T, n_samples, f) || I > fullcov_max_inputs()) return BSG_EINVAL;
+    if (F * T * I == 0) return BSG_OK;
+    if (!vis_in || !vis_out || !autos || (uintptr_t)vis_in % 8 || (uintptr_t)vis_out % 8 ||
+        (uintptr_t)autos % 4 || F * T > (int64_t)INT32_MAX)
+        return BSG_EINVAL;
+    const double c = (12.0 * f) / (2.0 * n_samples);
+    return hip_status(launch_fullcov(static_cast<const float *>(vis_in), autos, F, I, T, c,
+                                     static_cast<float *>(vis_out), nullptr,
+                                     static_cast<hipStream_t>(stream)));
+}
+
 int bsg_round_to_noise_i32(const void *vis_in, void *vis_out, const int32_t *autos, int64_t F,
                            int64_t I, int64_t T, const int32_t *prod_map, double n_samples,
                            double f, void *stream)

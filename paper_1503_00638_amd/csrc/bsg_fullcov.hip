@@ -1,0 +1,200 @@
+// Full-covariance noise for small arrays (Masui et al., Section 3.1, Eqs.
+// rad_full1-3 and Eq. noise): per (frequency, time) the covariance of the
+// I^2 real degrees of freedom of the visibilities (Re of every product, Im
+// of every cross product, in product order), the noise of each degree of
+// freedom s_k^2 = 1 / (C^-1)_kk, and the rounding of Section 3.2 with
+// G2 = 12 f s_k^2.  With Q = 2N C this is G2 = c / (Q^-1)_kk, c = (12 f)/(2N).
+//
+// One workgroup per sample holds Q in LDS (D = I^2 <= 121, so at most
+// 117 KiB): the Hermitian V of the sample, Q from it, a right-looking
+// Cholesky factorisation Q = L L^T in place (a step per column, the
+// trailing update spread over the workgroup), then M = L^-1 one column per
+// thread (stored transposed in the free upper triangle) and
+// (Q^-1)_kk = sum_i M_ik^2.  Every element sees its operations in the same
+// order as a plain serial implementation (sums in increasing index order),
+// so the results are reproducible bit for bit.  A sample whose Q is not
+// positive definite gets no estimate and is left unchanged.
+#include <cmath>
+
+#include "bsg_internal.hpp"
+#include "bsg_round_dev.hpp"
+
+namespace bsg {
+
+namespace {
+
+constexpr int kMaxInputs = 11; // D = 121 degrees of freedom, 117 KiB of LDS
+
+struct Cplx {
+    double re, im;
+};
+
+__device__ __forceinline__ Cplx mul_conj(Cplx a, Cplx b) // a * conj(b)
+{
+    return Cplx{a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+
+// inputs (i, j) of product p in upper-triangle row-major order
+__device__ __forceinline__ void pair_of(int I, int p, int &i, int &j)
+{
+    i = 0;
+    while (p >= I - i) {
+        p -= I - i;
+        ++i;
+    }
+    j = i + p;
+}
+
+struct FullcovArgs {
+    const float2 *vis;
+    const float *autos;
+    int64_t F, T;
+    int I, P, D;
+    double c;
+    float2 *vis_out;  // nullptr: only the inverse diagonal
+    double *qdiag;    // [F][T][D] or nullptr
+};
+
+__global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
+{
+    extern __shared__ double smem[];
+    const int D = a.D, I = a.I, P = a.P;
+    double *Q = smem;                     // D x D, row major
+    double *Mdiag = Q + D * D;            // D
+    Cplx *V = reinterpret_cast<Cplx *>(Mdiag + D); // I x I
+    int *dof = reinterpret_cast<int *>(V + I * I);  // D: product * 2 + (Im ? 1 : 0)
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int64_t s = blockIdx.x; // sample (fr, t)
+    const int64_t fr = s / a.T, t = s - fr * a.T;
+
+    if (tid == 0) {
+        bad = 0;
+        int k = 0;
+        for (int p = 0; p < P; ++p) {
+            int i, j;
+            pair_of(I, p, i, j);
+            dof[k++] = 2 * p;
+            if (i != j) dof[k++] = 2 * p + 1;
+        }
+    }
+    for (int e = tid; e < I * I; e += blockDim.x) {
+        const int x = e / I, y = e - x * I;
+        Cplx v;
+        if (x == y) {
+            v.re = a.autos[(fr * I + x) * a.T + t];
+            v.im = 0.0;
+        } else {
+            const int lo = x < y ? x : y, hi = x < y ? y : x;
+            const int p = lo * I - lo * (lo - 1) / 2 + (hi - lo);
+            const float2 w = a.vis[(fr * P + p) * a.T + t];
+            v.re = w.x;
+            v.im = x < y ? (double)w.y : -(double)w.y;
+        }
+        V[e] = v;
+    }
+    __syncthreads();
+
+    // Q = 2N C (Eqs. rad_full1-3)
+    for (int e = tid; e < D * D; e += blockDim.x) {
+        const int x = e / D, y = e - x * D;
+        int i, j, g, h;
+        pair_of(I, dof[x] >> 1, i, j);
+        pair_of(I, dof[y] >> 1, g, h);
+        const bool ix = dof[x] & 1, iy = dof[y] & 1;
+        const Cplx A = mul_conj(V[i * I + g], V[j * I + h]);
+        const Cplx B = mul_conj(V[i * I + h], V[j * I + g]);
+        double q;
+        if (!ix && !iy) {
+            q = A.re + B.re;
+        } else if (ix && iy) {
+            q = A.re - B.re;
+        } else if (!ix) {
+            q = -A.im + B.im;
+        } else { // (Im ij, Re gh) is the (Re gh, Im ij) element
+            const Cplx A2 = mul_conj(V[g * I + i], V[h * I + j]);
+            const Cplx B2 = mul_conj(V[g * I + j], V[h * I + i]);
+            q = -A2.im + B2.im;
+        }
+        Q[e] = q;
+    }
+    __syncthreads();
+
+    // Cholesky, right-looking, in place in the lower triangle
+    for (int k = 0; k < D; ++k) {
+        const double d = Q[k * D + k];
+        if (!(d > 0.0) || d == __builtin_inf()) { // uniform: every thread reads the same d
+            if (tid == 0) bad = 1;
+            break;
+        }
+        const double lkk = sqrt(d);
+        __syncthreads(); // everyone has read Q[k][k]
+        if (tid == 0) Q[k * D + k] = lkk;
+        for (int i = k + 1 + tid; i < D; i += blockDim.x) Q[i * D + k] = Q[i * D + k] / lkk;
+        __syncthreads();
+        // trailing lower triangle, rows and columns k+1 .. D-1, on a 16 x 16
+        // grid of threads
+        for (int i = k + 1 + (tid >> 4); i < D; i += 16)
+            for (int j = k + 1 + (tid & 15); j <= i; j += 16)
+                Q[i * D + j] = Q[i * D + j] - Q[i * D + k] * Q[j * D + k];
+        __syncthreads();
+    }
+    __syncthreads();
+    const bool failed = bad != 0;
+
+    // M = L^-1, column j by thread j; M_ij (i > j) kept at Q[j][i]
+    double qk = __builtin_nan("");
+    if (!failed) {
+        for (int j = tid; j < D; j += blockDim.x) {
+            const double mjj = 1.0 / Q[j * D + j];
+            Mdiag[j] = mjj;
+            for (int i = j + 1; i < D; ++i) {
+                double acc = Q[i * D + j] * mjj;
+                for (int m = j + 1; m < i; ++m) acc = acc + Q[i * D + m] * Q[j * D + m];
+                const double mij = -acc / Q[i * D + i];
+                Q[j * D + i] = mij;
+            }
+            // (Q^-1)_jj = sum_{i >= j} M_ij^2 in increasing i
+            double q = 0.0;
+            q = q + mjj * mjj;
+            for (int i = j + 1; i < D; ++i) q = q + Q[j * D + i] * Q[j * D + i];
+            if (j == tid) qk = q;
+            if (a.qdiag) a.qdiag[s * D + j] = q;
+        }
+    } else if (a.qdiag) {
+        for (int j = tid; j < D; j += blockDim.x) a.qdiag[s * D + j] = __builtin_nan("");
+    }
+    if (!a.vis_out) return;
+    // round degree of freedom k = tid (D <= 121 < 256 threads)
+    if (tid < D) {
+        const int p = dof[tid] >> 1;
+        const bool im = dof[tid] & 1;
+        const int64_t e = (fr * P + p) * a.T + t;
+        const float x = im ? a.vis[e].y : a.vis[e].x;
+        const uint32_t r = round_noise_bits(__float_as_uint(x), a.c / qk);
+        float *o = reinterpret_cast<float *>(a.vis_out + e);
+        o[im ? 1 : 0] = __uint_as_float(r);
+        int i, j;
+        pair_of(I, p, i, j);
+        if (i == j) o[1] = a.vis[e].y; // Im of an auto is copied
+    }
+}
+
+} // namespace
+
+int fullcov_max_inputs() { return kMaxInputs; }
+
+hipError_t launch_fullcov(const float *vis, const float *autos, int64_t F, int64_t I, int64_t T,
+                          double c, float *vis_out, double *qdiag, hipStream_t s)
+{
+    const int D = (int)(I * I), P = (int)(I * (I + 1) / 2);
+    if (F * T == 0 || D == 0) return hipSuccess;
+    FullcovArgs a{reinterpret_cast<const float2 *>(vis), autos, F, T, (int)I, P, D, c,
+                  reinterpret_cast<float2 *>(vis_out), qdiag};
+    const size_t lds = sizeof(double) * ((size_t)D * D + D) + sizeof(Cplx) * (size_t)(I * I) +
+                       sizeof(int) * (size_t)D;
+    hipLaunchKernelGGL(k_fullcov, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+} // namespace bsg

@@ -168,6 +168,9 @@ struct RoundParams {
 hipError_t launch_round(const float *vin, float *vout, const RoundParams &rp, hipStream_t s);
 hipError_t launch_round_i32(const int32_t *vin, int32_t *vout, const RoundParams &rp, hipStream_t s);
 hipError_t launch_noise_comp(const float *vis, const RoundParams &rp, double *scale, hipStream_t s);
+int fullcov_max_inputs();
+hipError_t launch_fullcov(const float *vis, const float *autos, int64_t F, int64_t I, int64_t T,
+                          double c, float *vis_out, double *qdiag, hipStream_t s);
 hipError_t launch_shuffle(const uint8_t *in, uint8_t *out, const Layout &L, bool inverse,
                           hipStream_t s);
 hipError_t launch_byteshuffle(const uint8_t *in, uint8_t *out, const Layout &L, bool inverse,

@@ -1,0 +1,71 @@
+"""GPU parity for the full-covariance noise of small arrays (Section 3.1,
+Eqs. rad_full1-3, Eq. noise): the inverse-covariance diagonal and the
+rounding with it equal the oracle bit for bit (both run the same Cholesky
+and triangular-inverse steps with sums in increasing index order)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_00638_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = synth.N_SAMPLES_DEFAULT
+
+
+@pytest.fixture(scope="module")
+def bsg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1503_00638_amd as m
+    m.load()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CASES = [(2, 1, 3, 0, 0.0), (3, 2, 5, 1, 0.4), (2, 4, 7, 2, 2.0), (4, 8, 16, 3, 0.4),
+         (1, 11, 3, 4, 0.4), (2, 5, 33, 5, 20.0)]
+
+
+@pytest.mark.parametrize("F,I,T,seed,source", CASES)
+def test_inverse_diagonal_parity(bsg, F, I, T, seed, source):
+    vis, autos = synth.gen_vis_point_source(F, I, T, seed, source)
+    ref = oracle.fullcov_inverse_diag(vis, autos)
+    got = host(bsg.fullcov_inverse_diag(dev(vis), dev(autos)))
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("F,I,T,seed,source", CASES)
+def test_fullcov_rounding_parity(bsg, F, I, T, seed, source):
+    vis, autos = synth.gen_vis_point_source(F, I, T, seed, source)
+    for f in (0.01, 1e-4):
+        ref = oracle.round_to_noise_fullcov(vis, autos, N, f)
+        got = host(bsg.round_to_noise_fullcov(dev(vis), dev(autos), N, f))
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), f
+
+
+def test_fullcov_singular_and_in_place(bsg):
+    vis, autos = synth.gen_vis(3, 6, 9, 7)
+    autos[1, 2, 4] = 0.0
+    autos[2, 0, 0] = np.nan
+    ref = oracle.round_to_noise_fullcov(vis, autos, N, 0.01)
+    dv = dev(vis)
+    bsg.round_to_noise_fullcov(dv, dev(autos), N, 0.01, out=dv)
+    assert np.array_equal(host(dv).view(np.uint32), ref.view(np.uint32))
+    q = host(bsg.fullcov_inverse_diag(dev(vis), dev(autos)))
+    assert np.isnan(q[1, 4]).all() and np.isnan(q[2, 0]).all() and np.isfinite(q[0]).all()
+
+
+def test_fullcov_rejects_large_arrays(bsg):
+    vis, autos = synth.gen_vis(1, 12, 2, 0)
+    with pytest.raises(bsg.BsgError):
+        bsg.round_to_noise_fullcov(dev(vis), dev(autos), N, 0.01)
