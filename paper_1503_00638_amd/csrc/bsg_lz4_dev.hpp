@@ -314,23 +314,32 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
             m[cc] = __ballot(ok);
         }
 
-        // Greedy parse of the matches that start inside this group.
+        // Greedy parse of the matches that start inside this group.  Lane w
+        // (< NC) holds chunk w's match mask, so the first match at or after
+        // the parse position is one ballot away.
+        uint32_t mlo = 0, mhi = 0;
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            mlo = lane == cc ? (uint32_t)m[cc] : mlo;
+            mhi = lane == cc ? (uint32_t)(m[cc] >> 32) : mhi;
+        }
         for (;;) {
             const int start = max(pnext, g0);
             if (start > last_take || start >= g0 + kGroup) break;
-            int q = -1, c = 0;
+            const int rel = start - g0, wst = rel >> 6;
+            uint64_t mm = ((uint64_t)mhi << 32) | mlo;
+            mm = lane < wst ? 0ull : (lane == wst ? mm & (~0ull << (rel & 63)) : mm);
+            const uint64_t nz = __ballot(mm != 0);
+            if (nz == 0) break;
+            const int w = __builtin_ctzll(nz);
+            const uint64_t mw = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mm >> 32), w) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mm, w);
+            const int bit = __builtin_ctzll(mw);
+            const int q = g0 + w * kChunk + bit;
+            uint32_t cv = cand[0];
 #pragma unroll
-            for (int w = 0; w < NC; ++w) {
-                const int wb = g0 + w * kChunk;
-                uint64_t mm = m[w];
-                if (start > wb) mm = start - wb >= kChunk ? 0 : (mm & (~0ull << (start - wb)));
-                if (q < 0 && mm) {
-                    const int bit = __builtin_ctzll(mm);
-                    q = wb + bit;
-                    c = __builtin_amdgcn_readlane((int)cand[w], bit) - 1;
-                }
-            }
-            if (q < 0) break;
+            for (int cc = 1; cc < NC; ++cc) cv = w == cc ? cand[cc] : cv;
+            const int c = __builtin_amdgcn_readlane((int)cv, bit) - 1;
             const int L = __builtin_amdgcn_readfirstlane(
                 extend_match<MAXB>(b32, c, q, kMinTake, n - kLastLiterals - q));
             op = emit(dst, op, b32, anchor, q - anchor, q - c, L, false);
