@@ -285,33 +285,38 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
         }
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc) {
+            // (chunks past last_q only insert positions that no lookup sees)
             const int c0 = g0 + cc * kChunk;
-            cand[cc] = 0;
-            if (c0 <= last_q) {
-                const int p = c0 + lane;
-                const bool ins = p <= last_ins;
-                const uint32_t h = (v[cc] * kHashMult) >> (32 - kHashBits);
-                if (p <= last_q) cand[cc] = table[h];
-                // when every inserted position of the chunk holds the same 4
-                // bytes they share one entry: only the largest position writes
-                const uint32_t v0 = __builtin_amdgcn_readfirstlane(v[cc]);
-                const bool uni = __ballot(ins && v[cc] != v0) == 0;
-                const int last_lane = last_ins - c0 < kChunk - 1 ? last_ins - c0 : kChunk - 1;
-                if (ins && (!uni || lane == last_lane)) atomicMax(&table[h], (uint32_t)(p + 1));
-            }
+            const int p = c0 + lane;
+            const bool ins = p <= last_ins;
+            const uint32_t h = (v[cc] * kHashMult) >> (32 - kHashBits);
+            const uint32_t t = table[h];
+            cand[cc] = p <= last_q ? t : 0u;
+            // inserted positions that hold lane 0's 4 bytes share one entry:
+            // lane 0 alone writes the largest of them.  A lane with nothing
+            // to insert takes a max with 0 at an entry of its own: no effect,
+            // no branch and no two lanes on one address.
+            const uint32_t v0 = __builtin_amdgcn_readfirstlane(v[cc]);
+            const uint64_t same = __ballot(ins && v[cc] == v0);
+            const uint32_t top = (uint32_t)(c0 + 64 - __builtin_clzll(same | 1ull));
+            uint32_t val = lane == 0 ? top : (uint32_t)(p + 1);
+            val = ins && (v[cc] != v0 || lane == 0) ? val : 0u;
+            atomicMax(&table[val != 0 ? h : (uint32_t)lane], val);
         }
         // (branch-free so that the 24 reads of the group issue back to back:
         // a lane without a candidate reads position 0 and is masked after)
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc) {
             const int p = g0 + cc * kChunk + lane;
-            const int c = cand[cc] != 0 ? (int)cand[cc] - 1 : 0;
+            const uint32_t cn = p <= last_take ? cand[cc] : 0u;
+            const int c = cn != 0 ? (int)cn - 1 : 0;
             const uint32_t *d = b32 + (c >> 2);
             const uint32_t e0 = d[0], e1 = d[1], e2 = d[2];
-            const bool ok = (p <= last_take) & (cand[cc] != 0) &
-                            (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) == v[cc]) &
-                            (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) == v2[cc]);
-            m[cc] = __ballot(ok);
+            // zero when the candidate exists and its 8 bytes equal those at p
+            const uint32_t x = (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) ^ v[cc]) |
+                               (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) ^ v2[cc]) |
+                               ((cn - 1u) >> 31);
+            m[cc] = __ballot(x == 0);
         }
 
         // Greedy parse of the matches that start inside this group.  Lane w
