@@ -16,35 +16,16 @@ constexpr int kSmallBlock = 8192;     // LDS-resident block for the hot path
 constexpr int kLargeBlock = 65536;
 constexpr int kTile = 1024;           // blocks per scan tile
 
+// DPP controls: lane i reads lane i + 1 of the wave; lane i reads lane i - n
+// of its row of 16 (none: 0); lane 15 (31) feeds the next row (rows 2, 3).
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
 __device__ __forceinline__ uint32_t lds_le32(const uint32_t *b32, int pos)
 {
     const uint32_t w0 = b32[pos >> 2], w1 = b32[(pos >> 2) + 1];
     return __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)(pos & 3));
-}
-
-// Write the low n (0..4) bytes of v at byte position pos of b8 (LDS or HBM).
-// mis = address & 3 is the same for every lane of a copy, so the widest
-// aligned stores are chosen uniformly.
-__device__ __forceinline__ void put4(uint8_t *b8, int pos, uint32_t v, int n, int mis)
-{
-    if (n == 4) {
-        if (mis == 0) {
-            *reinterpret_cast<uint32_t *>(b8 + pos) = v;
-            return;
-        }
-        if (mis == 2) {
-            *reinterpret_cast<uint16_t *>(b8 + pos) = (uint16_t)v;
-            *reinterpret_cast<uint16_t *>(b8 + pos + 2) = (uint16_t)(v >> 16);
-            return;
-        }
-        b8[pos] = (uint8_t)v;
-        *reinterpret_cast<uint16_t *>(b8 + pos + 1) = (uint16_t)(v >> 8);
-        b8[pos + 3] = (uint8_t)(v >> 24);
-        return;
-    }
-    if (n > 0) b8[pos] = (uint8_t)v;
-    if (n > 1) b8[pos + 1] = (uint8_t)(v >> 8);
-    if (n > 2) b8[pos + 2] = (uint8_t)(v >> 16);
 }
 
 // ---- stage the block into LDS as bit planes -------------------------------
@@ -166,42 +147,103 @@ __device__ __forceinline__ void stage_block(const uint8_t *__restrict__ src, int
     }
 }
 
-// ---- LZ4 emission (wave-cooperative, uniform control flow) ------------------
-__device__ __forceinline__ void put_len_ext(uint8_t *dst, int op, int r, int next)
+// ---- LZ4 emission, one sequence per lane ------------------------------------
+// Exclusive prefix sum of x over the wave's lanes; total = the sum of all.
+// Inclusive sums within rows of 16 lanes by shifts of 1, 2, 4 and 8, then
+// the row totals carried over by the broadcasts of lanes 15 and 31.
+__device__ __forceinline__ int wave_excl_scan(int x, int &total)
 {
-    // r = length - 15 >= 0 encoded as next bytes: 255 ... 255, r % 255
-    for (int i = threadIdx.x; i < next; i += kWave)
-        dst[op + i] = (i < next - 1) ? (uint8_t)255 : (uint8_t)(r % 255);
+    int s = x;
+    s += __builtin_amdgcn_update_dpp(0, s, kDppRowShr1, 0xF, 0xF, true);
+    s += __builtin_amdgcn_update_dpp(0, s, kDppRowShr2, 0xF, 0xF, true);
+    s += __builtin_amdgcn_update_dpp(0, s, kDppRowShr4, 0xF, 0xF, true);
+    s += __builtin_amdgcn_update_dpp(0, s, kDppRowShr8, 0xF, 0xF, true);
+    s += __builtin_amdgcn_update_dpp(0, s, kDppRowBcast15, 0xA, 0xF, false);
+    s += __builtin_amdgcn_update_dpp(0, s, kDppRowBcast31, 0xC, 0xF, false);
+    total = __builtin_amdgcn_readlane(s, kWave - 1);
+    return s - x;
 }
 
-__device__ __forceinline__ int emit(uint8_t *__restrict__ dst, int op, const uint32_t *b32, int lit,
-                                    int ll, int offset, int ml, bool last)
+// lds_le32 for a position as far as 3 bytes before the block: the bytes
+// before it come out undefined.
+__device__ __forceinline__ uint32_t lds_le32_head(const uint32_t *b32, int pos)
+{
+    const int wi = pos >> 2;
+    const uint32_t w0 = b32[wi < 0 ? 0 : wi], w1 = b32[wi + 1];
+    return __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)(pos & 3));
+}
+
+// Write the ns (<= 64) sequences that lanes 0 .. ns-1 hold (lane j: the
+// literals [lit, lit + ll) of the block at b32, then a match of ml bytes at
+// distance off; ml == 0 marks the block's last sequence, literals only) from
+// byte op of the 16-byte aligned slot dst; returns the byte after them.
+// Each lane writes its own token, offset and length bytes; then the wave
+// copies the literal runs, 16 output bytes per lane per step: whole dwords
+// where a run covers them, single bytes at a run's ends.  The block must be
+// readable 4 bytes past every run.
+__device__ __forceinline__ int emit_sequences(uint8_t *__restrict__ dst, int op, const uint32_t *b32,
+                                              int ns, int lit, int ll, int off, int ml)
 {
     const int lane = threadIdx.x;
+    const bool act = lane < ns;
+    const bool last = ml == 0;
     const int mlc = last ? 0 : ml - kMinMatch;
     const int lext = ll >= 15 ? (ll - 15) / 255 + 1 : 0;
-    if (lane == 0) dst[op] = (uint8_t)(((ll < 15 ? ll : 15) << 4) | (mlc < 15 ? mlc : 15));
-    put_len_ext(dst, op + 1, ll - 15, lext);
-    op += 1 + lext;
-    // literals, 4 bytes per lane per step
-    uint8_t *lp = dst + op;
-    const int mis = (int)((uintptr_t)lp & 3);
-    for (int k = 0; k < ll; k += 4 * kWave) {
-        const int pos = k + 4 * lane;
-        if (pos < ll) put4(lp, pos, lds_le32(b32, lit + pos), ll - pos < 4 ? ll - pos : 4, mis);
+    const int mext = mlc >= 15 ? (mlc - 15) / 255 + 1 : 0;
+    const int hsz = 1 + lext, tsz = last ? 0 : 2 + mext;
+    int total;
+    const int start = op + wave_excl_scan(act ? hsz + ll + tsz : 0, total);
+
+    // token, literal-length bytes; offset, match-length bytes
+    const uint32_t tok = (uint32_t)(((ll < 15 ? ll : 15) << 4) | (mlc < 15 ? mlc : 15));
+    const uint32_t lrem = (uint32_t)(ll - 15 - 255 * (lext - 1));
+    const uint32_t mrem = (uint32_t)(mlc - 15 - 255 * (mext - 1));
+    const int tpos = start + hsz + ll;
+    const int fmax = act ? (hsz > tsz ? hsz : tsz) : 0;
+    for (int k = 0; __ballot(k < fmax) != 0; ++k) {
+        if (act && k < hsz) dst[start + k] = (uint8_t)(k == 0 ? tok : (k < lext ? 255u : lrem));
+        if (act && k < tsz)
+            dst[tpos + k] = (uint8_t)(k == 0 ? (uint32_t)off & 255u
+                                             : (k == 1 ? (uint32_t)off >> 8 : (k < tsz - 1 ? 255u : mrem)));
     }
-    op += ll;
-    if (!last) {
-        if (lane == 0) {
-            dst[op] = (uint8_t)(offset & 255);
-            dst[op + 1] = (uint8_t)(offset >> 8);
+
+    // literal runs: task t of the wave is the 16 output bytes (ls_j / 16) +
+    // t - first_j of the sequence j with first_j <= t < first_{j+1}
+    const int ls = start + hsz;
+    const int nd = act && ll > 0 ? ((ls + ll - 1) >> 4) - (ls >> 4) + 1 : 0;
+    int ndt;
+    const int first = wave_excl_scan(nd, ndt);
+    uint32_t *dst32 = reinterpret_cast<uint32_t *>(dst);
+    for (int t0 = 0; t0 < ndt; t0 += kWave) {
+        const int t = t0 + lane;
+        int j = 0; // the last sequence whose first task is <= t
+#pragma unroll
+        for (int st = kWave / 2; st >= 1; st >>= 1) {
+            const int fj = __shfl(first, j + st);
+            j = j + st < ns && fj <= t ? j + st : j;
         }
-        op += 2;
-        const int mext = mlc >= 15 ? (mlc - 15) / 255 + 1 : 0;
-        put_len_ext(dst, op, mlc - 15, mext);
-        op += mext;
+        const int ls_j = __shfl(ls, j), ll_j = __shfl(ll, j);
+        const int lit_j = __shfl(lit, j), f_j = __shfl(first, j);
+        if (t < ndt) {
+            const int u = (ls_j >> 4) + t - f_j;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int w = 4 * u + k;
+                const int b0 = ls_j - 4 * w, b1 = b0 + ll_j; // the run's bytes in dword w: [b0, b1)
+                if (b1 > 0 && b0 < 4) {
+                    const uint32_t val = lds_le32_head(b32, lit_j - b0);
+                    if (b0 <= 0 && b1 >= 4) {
+                        dst32[w] = val;
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (i >= b0 && i < b1) dst[4 * w + i] = (uint8_t)(val >> (8 * i));
+                    }
+                }
+            }
+        }
     }
-    return op;
+    return op + total;
 }
 
 // ---- the fixed-rule LZ4 encoder of one LDS-resident block -----------------
@@ -271,6 +313,8 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
     const int last_take = last_q - 1;          // ... and still reach 8 bytes
     const int last_ins = n - kMinMatch;        // last position with a defined hash
     int anchor = 0, pnext = 0, op = 0;
+    // sequences found and not yet written: lane j holds sequence j
+    int ns = 0, s_lit = 0, s_ll = 0, s_off = 0, s_ml = 0;
     for (int g0 = 0; g0 <= last_q; g0 += kGroup) {
         uint32_t v[NC], v2[NC], cand[NC];
         uint64_t m[NC];
@@ -292,15 +336,16 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
             const uint32_t h = (v[cc] * kHashMult) >> (32 - kHashBits);
             const uint32_t t = table[h];
             cand[cc] = p <= last_q ? t : 0u;
-            // inserted positions that hold lane 0's 4 bytes share one entry:
-            // lane 0 alone writes the largest of them.  A lane with nothing
-            // to insert takes a max with 0 at an entry of its own: no effect,
-            // no branch and no two lanes on one address.
-            const uint32_t v0 = __builtin_amdgcn_readfirstlane(v[cc]);
-            const uint64_t same = __ballot(ins && v[cc] == v0);
-            const uint32_t top = (uint32_t)(c0 + 64 - __builtin_clzll(same | 1ull));
-            uint32_t val = lane == 0 ? top : (uint32_t)(p + 1);
-            val = ins && (v[cc] != v0 || lane == 0) ? val : 0u;
+            // In a run of equal 4-byte values (a constant bit plane) only the
+            // run's last position writes: the entry takes the largest
+            // position either way, and atomics of many lanes on one address
+            // would be serialised.  The next lane's value comes from a DPP
+            // wave shift (lane i reads lane i + 1).  A lane with nothing to
+            // insert takes a max with 0 at an entry of its own: no effect,
+            // no branch.
+            const uint32_t vn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[cc], kDppWaveShl1, 0xF, 0xF, false);
+            const bool run_on = lane != kWave - 1 && p + 1 <= last_ins && vn == v[cc];
+            const uint32_t val = ins && !run_on ? (uint32_t)(p + 1) : 0u;
             atomicMax(&table[val != 0 ? h : (uint32_t)lane], val);
         }
         // (branch-free so that the 24 reads of the group issue back to back:
@@ -347,13 +392,25 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
             const int c = __builtin_amdgcn_readlane((int)cv, bit) - 1;
             const int L = __builtin_amdgcn_readfirstlane(
                 extend_match<MAXB>(b32, c, q, kMinTake, n - kLastLiterals - q));
-            op = emit(dst, op, b32, anchor, q - anchor, q - c, L, false);
+            const bool me = lane == ns;
+            s_lit = me ? anchor : s_lit;
+            s_ll = me ? q - anchor : s_ll;
+            s_off = me ? q - c : s_off;
+            s_ml = me ? L : s_ml;
+            if (++ns == kWave) {
+                op = emit_sequences(dst, op, b32, ns, s_lit, s_ll, s_off, s_ml);
+                ns = 0;
+            }
             pnext = q + L;
             anchor = pnext;
         }
     }
-    op = emit(dst, op, b32, anchor, n - anchor, 0, 0, true);
-    return op;
+    // the last literals
+    const bool me = lane == ns;
+    s_lit = me ? anchor : s_lit;
+    s_ll = me ? n - anchor : s_ll;
+    s_ml = me ? 0 : s_ml;
+    return emit_sequences(dst, op, b32, ns + 1, s_lit, s_ll, s_off, s_ml);
 }
 
 // ---- sizes -> offsets -------------------------------------------------------
@@ -641,8 +698,11 @@ __device__ __forceinline__ void copy_slot(uint8_t *__restrict__ dst, const uint8
 }
 
 // ---- one block, start to end ----------------------------------------------
+// 12 KiB for the 8 KiB block, exactly 24 of the 512-byte units LDS is
+// allocated in (13 workgroups per CU).  Reads that run past the block land
+// in the table and are masked out.
 template <int MAXB> struct EncLds {
-    uint32_t blk32[MAXB / 4 + 4];
+    uint32_t blk32[MAXB / 4];
     uint32_t table[1 << kHashBits];
 };
 
@@ -655,7 +715,6 @@ __device__ __forceinline__ int encode_one(const uint8_t *__restrict__ src, int64
                                           uint8_t *__restrict__ slot, EncLds<MAXB> &L)
 {
     stage_block<EC, ROUND>(src, elems, E, reinterpret_cast<uint8_t *>(L.blk32), rp, first_elem);
-    if (threadIdx.x < 4) L.blk32[MAXB / 4 + threadIdx.x] = 0;
     __syncthreads();
     const int sz = encode_block<MAXB>(L.blk32, (int)(elems * E), L.table, slot);
     __syncthreads();
