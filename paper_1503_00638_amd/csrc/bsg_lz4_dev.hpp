@@ -42,14 +42,42 @@ __device__ __forceinline__ void stage_fast(const uint8_t *__restrict__ src, int6
         if constexpr (ROUND) {
             // E == 4: the unit is 32 float32 = 16 complex64 visibilities.
             VisCursor c = cursor_at(rp, (first_elem + u * 32) / 2);
+            if (c.t + 16 <= rp.T) {
+                // one product at one frequency: the autos (and factors) of
+                // the 16 times are consecutive, read from one base each
+                const float *pi = rp.autos + c.row_i + c.t;
+                const float *pj = rp.autos + c.row_j + c.t;
+                const bool is_auto = c.i == c.j;
+                float ai[16], aj[16];
+                double sc[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const float2 o = round_at(make_float2(__uint_as_float(w[2 * k]),
-                                                      __uint_as_float(w[2 * k + 1])),
-                                          c, rp);
-                w[2 * k] = __float_as_uint(o.x);
-                w[2 * k + 1] = __float_as_uint(o.y);
-                if (k < 15) cursor_advance(rp, c, 1);
+                for (int k = 0; k < 16; ++k) {
+                    ai[k] = pi[k];
+                    aj[k] = pj[k];
+                    sc[k] = 1.0;
+                }
+                if (rp.fscale) {
+                    const double *fs = rp.fscale + c.fr * rp.T + c.t;
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) sc[k] = fs[k];
+                }
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    double G2 = ((double)ai[k] * (double)aj[k]) * (is_auto ? rp.c_auto : rp.c);
+                    if (rp.fscale) G2 *= sc[k];
+                    w[2 * k] = round_noise_bits_nb(w[2 * k], G2);
+                    if (!is_auto) w[2 * k + 1] = round_noise_bits_nb(w[2 * k + 1], G2);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const float2 o = round_at(make_float2(__uint_as_float(w[2 * k]),
+                                                          __uint_as_float(w[2 * k + 1])),
+                                              c, rp);
+                    w[2 * k] = __float_as_uint(o.x);
+                    w[2 * k + 1] = __float_as_uint(o.y);
+                    if (k < 15) cursor_advance(rp, c, 1);
+                }
             }
         }
         unit_forward<E>(w);

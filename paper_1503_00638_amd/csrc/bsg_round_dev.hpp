@@ -57,6 +57,17 @@ __device__ __forceinline__ uint32_t round_noise_bits(uint32_t x, double G2)
     return round_bits(x, granularity_k(G2));
 }
 
+// round_noise_bits with both paths computed and one selected, for code
+// that rounds many values back to back (no branch per value).
+__device__ __forceinline__ uint32_t round_noise_bits_nb(uint32_t x, double G2)
+{
+    const int k = granularity_k(G2);
+    const double y = __builtin_ldexp((double)__uint_as_float(x), -k);
+    const uint32_t r = __float_as_uint((float)__builtin_ldexp(__builtin_rint(y), k));
+    const bool keep = !(G2 > 0.0) || G2 == __builtin_inf() || (x & 0x7F800000u) == 0x7F800000u;
+    return keep ? x : r;
+}
+
 // One complex visibility.  ai = V_ii, aj = V_jj at the same (f, t); sc is
 // the factor on G2 at that (f, t) (1 without compensation).  Both
 // components of a cross product share one G2 and one k.
