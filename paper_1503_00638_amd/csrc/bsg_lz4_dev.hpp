@@ -327,6 +327,65 @@ __device__ __forceinline__ int extend_match(const uint32_t *b32, int c, int q, i
 // entries to the chunk's positions (the wave's in-order LDS queue makes chunk
 // c see exactly chunks < c), (3) verify 8 bytes at every candidate, (4) parse
 // greedily with the candidate words in VGPRs and the match masks in SGPRs.
+// Hash, insert and verify the kGroup positions from g0 (Section 2.2's LZ4
+// stage with the fixed rule): cand[cc] is chunk cc's candidate for each lane
+// (position + 1, 0 = none) and m[cc] the mask of chunk cc's positions whose
+// candidate matches for 8 bytes.  FULL: the whole group lies at or below
+// last_take, so the bound checks drop out.
+template <int MAXB, bool FULL>
+__device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table, int g0, int last_q,
+                                           int last_take, int last_ins, uint32_t (&cand)[kGroup / kChunk],
+                                           uint64_t (&m)[kGroup / kChunk])
+{
+    constexpr int NC = kGroup / kChunk;
+    const int lane = threadIdx.x;
+    uint32_t v[NC], v2[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+        const int p = g0 + cc * kChunk + lane;
+        const int pc = FULL || p < MAXB ? p : MAXB;
+        const uint32_t *d = b32 + (pc >> 2);
+        const uint32_t d0 = d[0], d1 = d[1], d2 = d[2];
+        v[cc] = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)(pc & 3));
+        v2[cc] = __builtin_amdgcn_alignbyte(d2, d1, (uint32_t)(pc & 3));
+    }
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+        // (chunks past last_q only insert positions that no lookup sees)
+        const int c0 = g0 + cc * kChunk;
+        const int p = c0 + lane;
+        const bool ins = FULL || p <= last_ins;
+        const uint32_t h = (v[cc] * kHashMult) >> (32 - kHashBits);
+        const uint32_t t = table[h];
+        cand[cc] = FULL || p <= last_q ? t : 0u;
+        // In a run of equal 4-byte values (a constant bit plane) only the
+        // run's last position writes: the entry takes the largest position
+        // either way, and atomics of many lanes on one address would be
+        // serialised.  The next lane's value comes from a DPP wave shift
+        // (lane i reads lane i + 1).  A lane with nothing to insert takes a
+        // max with 0 at an entry of its own: no effect, no branch.
+        const uint32_t vn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[cc], kDppWaveShl1, 0xF, 0xF, false);
+        const bool run_on = lane != kWave - 1 && (FULL || p + 1 <= last_ins) && vn == v[cc];
+        const uint32_t val = ins && !run_on ? (uint32_t)(p + 1) : 0u;
+        atomicMax(&table[val != 0 ? h : (uint32_t)lane], val);
+    }
+    // (branch-free so that the 24 reads of the group issue back to back: a
+    // lane without a candidate reads position 0 and is masked after)
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+        const int p = g0 + cc * kChunk + lane;
+        const uint32_t cn = FULL || p <= last_take ? cand[cc] : 0u;
+        const int c = cn != 0 ? (int)cn - 1 : 0;
+        const uint32_t *d = b32 + (c >> 2);
+        const uint32_t e0 = d[0], e1 = d[1], e2 = d[2];
+        // zero when the candidate exists and its 8 bytes equal those at p
+        const uint32_t x = (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) ^ v[cc]) |
+                           (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) ^ v2[cc]) |
+                           ((cn - 1u) >> 31);
+        m[cc] = __ballot(x == 0);
+    }
+}
+
 template <int MAXB>
 __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t *table,
                                             uint8_t *__restrict__ dst)
@@ -344,53 +403,14 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
     // sequences found and not yet written: lane j holds sequence j
     int ns = 0, s_lit = 0, s_ll = 0, s_off = 0, s_ml = 0;
     for (int g0 = 0; g0 <= last_q; g0 += kGroup) {
-        uint32_t v[NC], v2[NC], cand[NC];
+        uint32_t cand[NC];
         uint64_t m[NC];
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) {
-            const int p = g0 + cc * kChunk + lane;
-            const int pc = p < MAXB ? p : MAXB;
-            const uint32_t *d = b32 + (pc >> 2);
-            const uint32_t d0 = d[0], d1 = d[1], d2 = d[2];
-            v[cc] = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)(pc & 3));
-            v2[cc] = __builtin_amdgcn_alignbyte(d2, d1, (uint32_t)(pc & 3));
-        }
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) {
-            // (chunks past last_q only insert positions that no lookup sees)
-            const int c0 = g0 + cc * kChunk;
-            const int p = c0 + lane;
-            const bool ins = p <= last_ins;
-            const uint32_t h = (v[cc] * kHashMult) >> (32 - kHashBits);
-            const uint32_t t = table[h];
-            cand[cc] = p <= last_q ? t : 0u;
-            // In a run of equal 4-byte values (a constant bit plane) only the
-            // run's last position writes: the entry takes the largest
-            // position either way, and atomics of many lanes on one address
-            // would be serialised.  The next lane's value comes from a DPP
-            // wave shift (lane i reads lane i + 1).  A lane with nothing to
-            // insert takes a max with 0 at an entry of its own: no effect,
-            // no branch.
-            const uint32_t vn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[cc], kDppWaveShl1, 0xF, 0xF, false);
-            const bool run_on = lane != kWave - 1 && p + 1 <= last_ins && vn == v[cc];
-            const uint32_t val = ins && !run_on ? (uint32_t)(p + 1) : 0u;
-            atomicMax(&table[val != 0 ? h : (uint32_t)lane], val);
-        }
-        // (branch-free so that the 24 reads of the group issue back to back:
-        // a lane without a candidate reads position 0 and is masked after)
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) {
-            const int p = g0 + cc * kChunk + lane;
-            const uint32_t cn = p <= last_take ? cand[cc] : 0u;
-            const int c = cn != 0 ? (int)cn - 1 : 0;
-            const uint32_t *d = b32 + (c >> 2);
-            const uint32_t e0 = d[0], e1 = d[1], e2 = d[2];
-            // zero when the candidate exists and its 8 bytes equal those at p
-            const uint32_t x = (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) ^ v[cc]) |
-                               (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) ^ v2[cc]) |
-                               ((cn - 1u) >> 31);
-            m[cc] = __ballot(x == 0);
-        }
+        // a group whose every position (and the one after it) may be
+        // inserted, looked up and taken needs no bound checks
+        if (g0 + kGroup <= last_take)
+            hash_group<MAXB, true>(b32, table, g0, last_q, last_take, last_ins, cand, m);
+        else
+            hash_group<MAXB, false>(b32, table, g0, last_q, last_take, last_ins, cand, m);
 
         // Greedy parse of the matches that start inside this group.  Lane w
         // (< NC) holds chunk w's match mask, so the first match at or after
