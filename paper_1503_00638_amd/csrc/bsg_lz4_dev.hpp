@@ -283,7 +283,18 @@ __device__ __forceinline__ int extend_match(const uint32_t *b32, int c, int q, i
 {
     const int lane = threadIdx.x;
     if (L >= maxL) return maxL;
-    {
+    if (L + 4 * kWave <= maxL) {
+        // the whole first step lies inside the block and the limit
+        const int o = L + 4 * lane;
+        const uint32_t diff = lds_le32(b32, c + o) ^ lds_le32(b32, q + o);
+        const uint64_t mm = __ballot(diff != 0);
+        if (mm) {
+            const int fl = __builtin_ctzll(mm);
+            const uint32_t dd = (uint32_t)__builtin_amdgcn_readlane((int)diff, fl);
+            return L + 4 * fl + (__builtin_ctz(dd) >> 3);
+        }
+        L += 4 * kWave;
+    } else {
         const int o = L + 4 * lane;
         const int pa = c + o < MAXB ? c + o : MAXB;
         const int pb = q + o < MAXB ? q + o : MAXB;
@@ -293,7 +304,7 @@ __device__ __forceinline__ int extend_match(const uint32_t *b32, int c, int q, i
         const uint64_t mm = __ballot(diff != 0);
         if (mm) {
             const int fl = __builtin_ctzll(mm);
-            const uint32_t dd = (uint32_t)__shfl((int)diff, fl);
+            const uint32_t dd = (uint32_t)__builtin_amdgcn_readlane((int)diff, fl);
             return L + 4 * fl + (__builtin_ctz(dd) >> 3);
         }
         L += 4 * kWave;
@@ -314,7 +325,7 @@ __device__ __forceinline__ int extend_match(const uint32_t *b32, int c, int q, i
         const uint64_t mm = __ballot(first < 16);
         if (mm) {
             const int fl = __builtin_ctzll(mm);
-            return L + 16 * fl + __shfl(first, fl);
+            return L + 16 * fl + __builtin_amdgcn_readlane(first, fl);
         }
         L += 16 * kWave;
     }
@@ -434,10 +445,21 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
                                 (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mm, w);
             const int bit = __builtin_ctzll(mw);
             const int q = g0 + w * kChunk + bit;
-            uint32_t cv = cand[0];
-#pragma unroll
-            for (int cc = 1; cc < NC; ++cc) cv = w == cc ? cand[cc] : cv;
-            const int c = __builtin_amdgcn_readlane((int)cv, bit) - 1;
+            // (a scalar switch: a select chain over the 8 chunks would cost
+            // 7 vector ops per match)
+            int cw;
+            switch (w) {
+            case 0: cw = __builtin_amdgcn_readlane((int)cand[0], bit); break;
+            case 1: cw = __builtin_amdgcn_readlane((int)cand[1], bit); break;
+            case 2: cw = __builtin_amdgcn_readlane((int)cand[2], bit); break;
+            case 3: cw = __builtin_amdgcn_readlane((int)cand[3], bit); break;
+            case 4: cw = __builtin_amdgcn_readlane((int)cand[4], bit); break;
+            case 5: cw = __builtin_amdgcn_readlane((int)cand[5], bit); break;
+            case 6: cw = __builtin_amdgcn_readlane((int)cand[6], bit); break;
+            default: cw = __builtin_amdgcn_readlane((int)cand[7], bit); break;
+            }
+            static_assert(NC == 8, "one case per chunk of the group");
+            const int c = cw - 1;
             const int L = __builtin_amdgcn_readfirstlane(
                 extend_match<MAXB>(b32, c, q, kMinTake, n - kLastLiterals - q));
             const bool me = lane == ns;
