@@ -18,6 +18,8 @@ constexpr int kTile = 1024;           // blocks per scan tile
 
 // DPP controls: lane i reads lane i + 1 of the wave; lane i reads lane i - n
 // of its row of 16 (none: 0); lane 15 (31) feeds the next row (rows 2, 3).
+typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+
 constexpr int kDppWaveShl1 = 0x130;
 constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
 constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
@@ -423,6 +425,10 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
         else
             hash_group<MAXB, false>(b32, table, g0, last_q, last_take, last_ins, cand, m);
 
+        u32x16 candv;
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) candv[cc] = cand[cc];
+
         // Greedy parse of the matches that start inside this group.  Lane w
         // (< NC) holds chunk w's match mask, so the first match at or after
         // the parse position is one ballot away.
@@ -445,21 +451,9 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
                                 (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mm, w);
             const int bit = __builtin_ctzll(mw);
             const int q = g0 + w * kChunk + bit;
-            // (a scalar switch: a select chain over the 8 chunks would cost
-            // 7 vector ops per match)
-            int cw;
-            switch (w) {
-            case 0: cw = __builtin_amdgcn_readlane((int)cand[0], bit); break;
-            case 1: cw = __builtin_amdgcn_readlane((int)cand[1], bit); break;
-            case 2: cw = __builtin_amdgcn_readlane((int)cand[2], bit); break;
-            case 3: cw = __builtin_amdgcn_readlane((int)cand[3], bit); break;
-            case 4: cw = __builtin_amdgcn_readlane((int)cand[4], bit); break;
-            case 5: cw = __builtin_amdgcn_readlane((int)cand[5], bit); break;
-            case 6: cw = __builtin_amdgcn_readlane((int)cand[6], bit); break;
-            default: cw = __builtin_amdgcn_readlane((int)cand[7], bit); break;
-            }
-            static_assert(NC == 8, "one case per chunk of the group");
-            const int c = cw - 1;
+            // (a 16-wide vector indexed with a uniform index compiles to
+            // one relative register move; 8 wide would be a select chain)
+            const int c = __builtin_amdgcn_readlane((int)candv[w], bit) - 1;
             const int L = __builtin_amdgcn_readfirstlane(
                 extend_match<MAXB>(b32, c, q, kMinTake, n - kLastLiterals - q));
             const bool me = lane == ns;
