@@ -340,70 +340,79 @@ __device__ __forceinline__ int extend_match(const uint32_t *b32, int c, int q, i
 // entries to the chunk's positions (the wave's in-order LDS queue makes chunk
 // c see exactly chunks < c), (3) verify 8 bytes at every candidate, (4) parse
 // greedily with the candidate words in VGPRs and the match masks in SGPRs.
-// Hash, insert and verify the kGroup positions from g0 (Section 2.2's LZ4
-// stage with the fixed rule): cand[cc] is chunk cc's candidate for each lane
-// (position + 1, 0 = none) and m[cc] the mask of chunk cc's positions whose
-// candidate matches for 8 bytes.  FULL: the whole group lies at or below
-// last_take, so the bound checks drop out.
+// Hash and insert the kGroup positions from g0 (the fixed rule of the LZ4
+// stage): per chunk cc of 64 positions, v/v2 hold bytes p..p+3 / p+4..p+7
+// of each lane's position p and cand the table entry it found (position +
+// 1, 0 = none) before the chunk's own inserts.  FULL: the whole group lies
+// at or below last_take, so the bound checks drop out.
 template <int MAXB, bool FULL>
 __device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table, int g0, int last_q,
-                                           int last_take, int last_ins, uint32_t (&cand)[kGroup / kChunk],
-                                           uint64_t (&m)[kGroup / kChunk])
+                                           int last_ins, u32x16 &vv, u32x16 &candv)
 {
     constexpr int NC = kGroup / kChunk;
     const int lane = threadIdx.x;
-    uint32_t v[NC], v2[NC];
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
         const int p = g0 + cc * kChunk + lane;
         const int pc = FULL || p < MAXB ? p : MAXB;
         const uint32_t *d = b32 + (pc >> 2);
         const uint32_t d0 = d[0], d1 = d[1], d2 = d[2];
-        v[cc] = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)(pc & 3));
-        v2[cc] = __builtin_amdgcn_alignbyte(d2, d1, (uint32_t)(pc & 3));
+        vv[cc] = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)(pc & 3));
+        vv[cc + NC] = __builtin_amdgcn_alignbyte(d2, d1, (uint32_t)(pc & 3));
     }
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
         // (chunks past last_q only insert positions that no lookup sees)
         const int c0 = g0 + cc * kChunk;
         const int p = c0 + lane;
+        const uint32_t v = vv[cc];
         const bool ins = FULL || p <= last_ins;
-        const uint32_t h = (v[cc] * kHashMult) >> (32 - kHashBits);
+        const uint32_t h = (v * kHashMult) >> (32 - kHashBits);
         const uint32_t t = table[h];
-        cand[cc] = FULL || p <= last_q ? t : 0u;
+        candv[cc] = FULL || p <= last_q ? t : 0u;
         // In a run of equal 4-byte values (a constant bit plane) only the
         // run's last position writes: the entry takes the largest position
         // either way, and atomics of many lanes on one address would be
         // serialised.  The next lane's value comes from a DPP wave shift
         // (lane i reads lane i + 1).  A lane with nothing to insert takes a
         // max with 0 at an entry of its own: no effect, no branch.
-        const uint32_t vn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v[cc], kDppWaveShl1, 0xF, 0xF, false);
-        const bool run_on = lane != kWave - 1 && (FULL || p + 1 <= last_ins) && vn == v[cc];
+        const uint32_t vn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppWaveShl1, 0xF, 0xF, false);
+        const bool run_on = lane != kWave - 1 && (FULL || p + 1 <= last_ins) && vn == v;
         const uint32_t val = ins && !run_on ? (uint32_t)(p + 1) : 0u;
         atomicMax(&table[val != 0 ? h : (uint32_t)lane], val);
     }
-    // (branch-free so that the 24 reads of the group issue back to back: a
-    // lane without a candidate reads position 0 and is masked after)
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc) {
-        const int p = g0 + cc * kChunk + lane;
-        const uint32_t cn = FULL || p <= last_take ? cand[cc] : 0u;
-        const int c = cn != 0 ? (int)cn - 1 : 0;
-        const uint32_t *d = b32 + (c >> 2);
-        const uint32_t e0 = d[0], e1 = d[1], e2 = d[2];
-        // zero when the candidate exists and its 8 bytes equal those at p
-        const uint32_t x = (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) ^ v[cc]) |
-                           (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) ^ v2[cc]) |
-                           ((cn - 1u) >> 31);
-        m[cc] = __ballot(x == 0);
-    }
 }
 
+// The mask of the chunk's positions (from c0) whose candidate matches for
+// 8 bytes and may be taken (<= last_take).  Branch-free: a lane without a
+// candidate reads position 0 and is masked after.
+__device__ __forceinline__ uint64_t verify_chunk(const uint32_t *b32, int c0, uint32_t v, uint32_t v2,
+                                                 uint32_t cand, int last_take)
+{
+    const int p = c0 + (int)threadIdx.x;
+    const uint32_t cn = c0 + kChunk - 1 <= last_take || p <= last_take ? cand : 0u;
+    const int c = cn != 0 ? (int)cn - 1 : 0;
+    const uint32_t *d = b32 + (c >> 2);
+    const uint32_t e0 = d[0], e1 = d[1], e2 = d[2];
+    // zero when the candidate exists and its 8 bytes equal those at p
+    const uint32_t x = (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) ^ v) |
+                       (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) ^ v2) | ((cn - 1u) >> 31);
+    return __ballot(x == 0);
+}
+
+// Greedy parse of one LDS-resident block of n bytes (n <= MAXB) into LZ4
+// sequences written to dst; returns the compressed size.  Positions are
+// hashed and inserted a group of 8 chunks at a time; a chunk's candidates
+// are verified only when the parse reaches it, so chunks inside a long
+// match are never verified.  Sequences are written 64 at a time.
+// (Per-chunk values sit in 16-wide register vectors: a uniform index into
+// one compiles to a relative register move.)
 template <int MAXB>
 __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t *table,
                                             uint8_t *__restrict__ dst)
 {
     constexpr int NC = kGroup / kChunk;
+    static_assert(2 * NC <= 16, "v and v2 of a group share one vector");
     const int lane = threadIdx.x;
     for (int i = lane; i < (1 << kHashBits) / 4; i += kWave)
         reinterpret_cast<uint4 *>(table)[i] = make_uint4(0, 0, 0, 0);
@@ -416,57 +425,43 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
     // sequences found and not yet written: lane j holds sequence j
     int ns = 0, s_lit = 0, s_ll = 0, s_off = 0, s_ml = 0;
     for (int g0 = 0; g0 <= last_q; g0 += kGroup) {
-        uint32_t cand[NC];
-        uint64_t m[NC];
+        u32x16 vv, candv;
         // a group whose every position (and the one after it) may be
         // inserted, looked up and taken needs no bound checks
         if (g0 + kGroup <= last_take)
-            hash_group<MAXB, true>(b32, table, g0, last_q, last_take, last_ins, cand, m);
+            hash_group<MAXB, true>(b32, table, g0, last_q, last_ins, vv, candv);
         else
-            hash_group<MAXB, false>(b32, table, g0, last_q, last_take, last_ins, cand, m);
+            hash_group<MAXB, false>(b32, table, g0, last_q, last_ins, vv, candv);
 
-        u32x16 candv;
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) candv[cc] = cand[cc];
-
-        // Greedy parse of the matches that start inside this group.  Lane w
-        // (< NC) holds chunk w's match mask, so the first match at or after
-        // the parse position is one ballot away.
-        uint32_t mlo = 0, mhi = 0;
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) {
-            mlo = lane == cc ? (uint32_t)m[cc] : mlo;
-            mhi = lane == cc ? (uint32_t)(m[cc] >> 32) : mhi;
-        }
-        for (;;) {
-            const int start = max(pnext, g0);
-            if (start > last_take || start >= g0 + kGroup) break;
-            const int rel = start - g0, wst = rel >> 6;
-            uint64_t mm = ((uint64_t)mhi << 32) | mlo;
-            mm = lane < wst ? 0ull : (lane == wst ? mm & (~0ull << (rel & 63)) : mm);
-            const uint64_t nz = __ballot(mm != 0);
-            if (nz == 0) break;
-            const int w = __builtin_ctzll(nz);
-            const uint64_t mw = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(mm >> 32), w) << 32) |
-                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mm, w);
-            const int bit = __builtin_ctzll(mw);
-            const int q = g0 + w * kChunk + bit;
-            // (a 16-wide vector indexed with a uniform index compiles to
-            // one relative register move; 8 wide would be a select chain)
-            const int c = __builtin_amdgcn_readlane((int)candv[w], bit) - 1;
-            const int L = __builtin_amdgcn_readfirstlane(
-                extend_match<MAXB>(b32, c, q, kMinTake, n - kLastLiterals - q));
-            const bool me = lane == ns;
-            s_lit = me ? anchor : s_lit;
-            s_ll = me ? q - anchor : s_ll;
-            s_off = me ? q - c : s_off;
-            s_ml = me ? L : s_ml;
-            if (++ns == kWave) {
-                op = emit_sequences(dst, op, b32, ns, s_lit, s_ll, s_off, s_ml);
-                ns = 0;
+        // chunk by chunk from the one holding the parse position
+        for (int cc = (pnext > g0 ? pnext - g0 : 0) >> 6; cc < NC; ++cc) {
+            const int c0 = g0 + cc * kChunk;
+            if (c0 > last_take) break;
+            const uint64_t mk = verify_chunk(b32, c0, vv[cc], vv[cc + NC], candv[cc], last_take);
+            for (;;) {
+                const int rel = pnext - c0;
+                const uint64_t mm = rel > 0 ? mk & (~0ull << rel) : mk;
+                if (mm == 0) break;
+                const int bit = __builtin_ctzll(mm);
+                const int q = c0 + bit;
+                const int c = __builtin_amdgcn_readlane((int)candv[cc], bit) - 1;
+                const int L = __builtin_amdgcn_readfirstlane(
+                    extend_match<MAXB>(b32, c, q, kMinTake, n - kLastLiterals - q));
+                const bool me = lane == ns;
+                s_lit = me ? anchor : s_lit;
+                s_ll = me ? q - anchor : s_ll;
+                s_off = me ? q - c : s_off;
+                s_ml = me ? L : s_ml;
+                if (++ns == kWave) {
+                    op = emit_sequences(dst, op, b32, ns, s_lit, s_ll, s_off, s_ml);
+                    ns = 0;
+                }
+                pnext = q + L;
+                anchor = pnext;
+                if (pnext >= c0 + kChunk) break;
             }
-            pnext = q + L;
-            anchor = pnext;
+            // skip the chunks the match covers (the loop steps to the next)
+            if (pnext >= c0 + kChunk) cc = (pnext - g0 - kChunk) >> 6;
         }
     }
     // the last literals
