@@ -20,6 +20,12 @@ constexpr int kTile = 1024;           // blocks per scan tile
 // of its row of 16 (none: 0); lane 15 (31) feeds the next row (rows 2, 3).
 typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 
+// The codec kernels run one wave per workgroup, and LDS accesses of one wave
+// take effect in program order: between their phases only the compiler must
+// not move memory accesses.  (A workgroup barrier would also wait for every
+// outstanding global load and store of the wave.)
+__device__ __forceinline__ void wave_sync() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
 constexpr int kDppWaveShl1 = 0x130;
 constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
 constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
@@ -416,7 +422,7 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
     const int lane = threadIdx.x;
     for (int i = lane; i < (1 << kHashBits) / 4; i += kWave)
         reinterpret_cast<uint4 *>(table)[i] = make_uint4(0, 0, 0, 0);
-    __syncthreads();
+    wave_sync();
 
     const int last_q = n - kMfLimit;           // last position a match may start at
     const int last_take = last_q - 1;          // ... and still reach 8 bytes
@@ -774,9 +780,9 @@ __device__ __forceinline__ int encode_one(const uint8_t *__restrict__ src, int64
                                           uint8_t *__restrict__ slot, EncLds<MAXB> &L)
 {
     stage_block<EC, ROUND>(src, elems, E, reinterpret_cast<uint8_t *>(L.blk32), rp, first_elem);
-    __syncthreads();
+    wave_sync();
     const int sz = encode_block<MAXB>(L.blk32, (int)(elems * E), L.table, slot);
-    __syncthreads();
+    wave_sync();
     return sz;
 }
 
@@ -820,11 +826,11 @@ __device__ __forceinline__ bool decode_one(const uint8_t *__restrict__ payload, 
             B[w0 + w] = v;
         }
     }
-    __syncthreads();
+    wave_sync();
     const bool ok = decode_inplace(B, base, base + len, ob);
-    __syncthreads();
+    wave_sync();
     if (ok) unstage_block<EC>(reinterpret_cast<const uint8_t *>(B), elems, E, dst, fast_out);
-    __syncthreads();
+    wave_sync();
     return ok;
 }
 
