@@ -112,9 +112,13 @@ __global__ __launch_bounds__(64) void k_pack(const uint8_t *__restrict__ slots, 
                                              int64_t tail_bytes, RoundParams rp, int round_tail,
                                              int64_t tail_first_elem)
 {
-    if (*d_nbytes < 0) return;
     const int64_t b = blockIdx.x;
     const uint64_t *off = reinterpret_cast<const uint64_t *>(out + kHeaderBytes);
+    // (the three loads issue together)
+    const int64_t nbytes = *d_nbytes;
+    const uint64_t ob = off[b];
+    const int sz = b < n_blocks ? sizes[b] : 0;
+    if (nbytes < 0) return;
     uint8_t *payload = out + kHeaderBytes + 8 * (n_blocks + 1);
     const int lane = threadIdx.x;
     if (b == n_blocks) {
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(64) void k_pack(const uint8_t *__restrict__ slots, 
         for (int64_t i = lane; i < tail_bytes; i += kWave) dst[i] = tail_src[i];
         return;
     }
-    copy_slot(payload + off[b], slots + b * slot_bytes, sizes[b]);
+    copy_slot(payload + ob, slots + b * slot_bytes, sz);
 }
 
 struct DecArgs {

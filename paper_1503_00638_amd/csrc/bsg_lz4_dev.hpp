@@ -742,22 +742,50 @@ template <int MAXB> constexpr int dec_buf_bytes() { return (MAXB + MAXB / 255 + 
 
 // Copy sz bytes from a 16-byte aligned slot (readable for at least sz + 8
 // bytes) to any byte address: head bytes until dst is 4-byte aligned, then
-// aligned dword stores assembled from two source dwords, then tail bytes.
+// aligned dwords assembled from two source dwords, then tail bytes.  Each
+// lane takes 4 destination dwords per step: one 16-byte load of its source
+// dwords plus the dword after them, and one 16-byte store.  All loads are
+// issued before the first store.
 __device__ __forceinline__ void copy_slot(uint8_t *__restrict__ dst, const uint8_t *__restrict__ src,
                                           int sz)
 {
+    constexpr int kSteps = 4; // 4 KiB per pass of the wave
     const int lane = threadIdx.x;
     const int mis = (int)((4 - ((uintptr_t)dst & 3)) & 3);
     const int head = mis < sz ? mis : sz;
     if (lane < head) dst[lane] = src[lane];
     const int body = (sz - head) / 4;
     const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src);
+    const uint4 *s128 = reinterpret_cast<const uint4 *>(src);
     uint32_t *d32 = reinterpret_cast<uint32_t *>(dst + head);
-    for (int w = lane; w < body; w += kWave) {
-        const int sp = head + 4 * w;
-        const uint32_t lo = s32[sp >> 2];
-        const uint32_t hi = s32[(sp >> 2) + 1];
-        d32[w] = __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)(sp & 3));
+    const uint32_t sh = (uint32_t)head;
+    for (int b0 = 0; b0 < body; b0 += 4 * kWave * kSteps) {
+        uint4 q[kSteps];
+        uint32_t nx[kSteps];
+#pragma unroll
+        for (int k = 0; k < kSteps; ++k) {
+            const int w = b0 + 4 * (kWave * k + lane); // first of the lane's 4 dwords
+            q[k] = make_uint4(0, 0, 0, 0);
+            nx[k] = 0;
+            if (w + 4 <= body) {
+                q[k] = s128[w >> 2];
+                nx[k] = s32[w + 4];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kSteps; ++k) {
+            const int w = b0 + 4 * (kWave * k + lane);
+            if (w + 4 <= body) {
+                const uint4 o = make_uint4(__builtin_amdgcn_alignbyte(q[k].y, q[k].x, sh),
+                                           __builtin_amdgcn_alignbyte(q[k].z, q[k].y, sh),
+                                           __builtin_amdgcn_alignbyte(q[k].w, q[k].z, sh),
+                                           __builtin_amdgcn_alignbyte(nx[k], q[k].w, sh));
+                *reinterpret_cast<uint4 *>(d32 + w) = o;
+            } else {
+                for (int j = w; j < body && j < w + 4; ++j)
+                    d32[j] = __builtin_amdgcn_alignbyte(s32[j + 1], s32[j], sh);
+            }
+        }
     }
     for (int i = head + 4 * body + lane; i < sz; i += kWave) dst[i] = src[i];
 }
