@@ -24,24 +24,65 @@ constexpr int kComplexPerThread = 8;
 // l, l + 64, ..., l + 448 of them, so every load and store instruction of the
 // wave touches 512 contiguous bytes.  The position (time, product, inputs,
 // auto rows) is found once per lane and then stepped.
+// Lane i of the grid rounds the kComplexPerThread consecutive visibilities
+// from e0 = i * kComplexPerThread.  When they lie in one product row at one
+// frequency (times t .. t + 7, the case whenever T is a multiple of 8), the
+// values and their autos are read with 16-byte loads from one base each and
+// every value is rounded without a branch; otherwise a cursor steps through
+// them one by one.
 __global__ __launch_bounds__(256) void k_round(const float2 *__restrict__ vin,
                                                float2 *__restrict__ vout, RoundParams rp,
-                                               int64_t n_complex)
+                                               int64_t n_complex, int aligned16)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    int64_t e = wave * (kWave * kComplexPerThread) + lane;
-    if (e >= n_complex) return;
-    VisCursor c = cursor_at(rp, e);
-    for (int k = 0;;) {
-        vout[e] = round_at(vin[e], c, rp);
-        e += kWave;
-        if (++k == kComplexPerThread || e >= n_complex) break;
-        cursor_advance(rp, c, kWave);
+    constexpr int K = kComplexPerThread;
+    const int64_t e0 = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * K;
+    if (e0 >= n_complex) return;
+    VisCursor c = cursor_at(rp, e0);
+    if (aligned16 && e0 + K <= n_complex && c.t + K <= rp.T) {
+        const float4 *v4 = reinterpret_cast<const float4 *>(vin + e0);
+        float4 v[K / 2];
+#pragma unroll
+        for (int k = 0; k < K / 2; ++k) v[k] = v4[k];
+        const float *pi = rp.autos + c.row_i + c.t;
+        const float *pj = rp.autos + c.row_j + c.t;
+        float ai[K], aj[K];
+        double sc[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            ai[k] = pi[k];
+            aj[k] = pj[k];
+            sc[k] = 1.0;
+        }
+        if (rp.fscale) {
+            const double *fs = rp.fscale + c.fr * rp.T + c.t;
+#pragma unroll
+            for (int k = 0; k < K; ++k) sc[k] = fs[k];
+        }
+        const bool is_auto = c.i == c.j;
+        float4 *o4 = reinterpret_cast<float4 *>(vout + e0);
+#pragma unroll
+        for (int k = 0; k < K / 2; ++k) {
+            uint32_t x[4] = {__float_as_uint(v[k].x), __float_as_uint(v[k].y), __float_as_uint(v[k].z),
+                             __float_as_uint(v[k].w)};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j = 2 * k + h;
+                double G2 = ((double)ai[j] * (double)aj[j]) * (is_auto ? rp.c_auto : rp.c);
+                if (rp.fscale) G2 *= sc[j];
+                x[2 * h] = round_noise_bits_nb(x[2 * h], G2);
+                if (!is_auto) x[2 * h + 1] = round_noise_bits_nb(x[2 * h + 1], G2);
+            }
+            o4[k] = make_float4(__uint_as_float(x[0]), __uint_as_float(x[1]), __uint_as_float(x[2]),
+                                __uint_as_float(x[3]));
+        }
+        return;
+    }
+    for (int k = 0; k < K && e0 + k < n_complex; ++k) {
+        if (k) cursor_advance(rp, c, 1);
+        vout[e0 + k] = round_at(vin[e0 + k], c, rp);
     }
 }
 
-// The same walk over integer visibilities (int32 re, im).
 __global__ __launch_bounds__(256) void k_round_i32(const int2 *__restrict__ vin,
                                                    int2 *__restrict__ vout, RoundParams rp,
                                                    int64_t n_complex)
@@ -107,9 +148,10 @@ hipError_t launch_round(const float *vin, float *vout, const RoundParams &rp, hi
     if (n_complex == 0) return hipSuccess;
     const int64_t waves = (n_complex + kWave * kComplexPerThread - 1) / (kWave * kComplexPerThread);
     const int64_t blocks = (waves * kWave + 255) / 256;
+    const int aligned16 = (((uintptr_t)vin | (uintptr_t)vout) & 15) == 0;
     hipLaunchKernelGGL(k_round, dim3((unsigned)blocks), dim3(256), 0, s,
                        reinterpret_cast<const float2 *>(vin), reinterpret_cast<float2 *>(vout),
-                       rp, n_complex);
+                       rp, n_complex, aligned16);
     return hipGetLastError();
 }
 
