@@ -835,24 +835,35 @@ __device__ __forceinline__ bool decode_one(const uint8_t *__restrict__ payload, 
     if (o0 > o1 || o1 > (uint64_t)payload_len || o1 - o0 > (uint64_t)lz4_bound(ob)) return false;
     const int len = (int)(o1 - o0);
     // stage the LZ4 block at the tail of the buffer with the same 4-byte
-    // phase as in HBM: aligned dword copies, the last one possibly partial
+    // phase as in HBM: the 16-byte lines holding it, one per lane and step
+    // (the dwords before the block land in the free output space, the
+    // last line's bytes past it in the padding; a line past in_end is read
+    // byte by byte)
     const uint8_t *src = payload + o0;
     const int s = (int)((uintptr_t)src & 3);
     const int base = ((kBuf - len - s) & ~3) + s;
-    const uint32_t *s32 = reinterpret_cast<const uint32_t *>(src - s);
-    const int words = (s + len + 3) >> 2;
-    const int w0 = (base - s) >> 2;
+    const int w0 = (base - s) >> 2;            // buffer dword of the stream dword holding src
+    const int s16 = (int)((uintptr_t)src & 15);
+    const uint4 *s128 = reinterpret_cast<const uint4 *>(src - s16);
+    const int lines = (s16 + len + 15) >> 4;
+    const int d0 = w0 - ((s16 - s) >> 2);      // buffer dword of the first line's first dword
     uint32_t *B = L.buf32 + 4; // the decode buffer; B[-1] is readable padding
-    for (int w = lane; w < words; w += kWave) {
-        const uint8_t *wp = reinterpret_cast<const uint8_t *>(s32 + w);
-        if (wp + 4 <= in_end) {
-            B[w0 + w] = s32[w];
+    for (int k = lane; k < lines; k += kWave) {
+        const uint8_t *lp = reinterpret_cast<const uint8_t *>(s128 + k);
+        uint4 v;
+        if (lp + 16 <= in_end) {
+            v = s128[k];
         } else {
-            uint32_t v = 0;
-            for (int k = 0; k < 4; ++k)
-                if (wp + k < in_end) v |= (uint32_t)wp[k] << (8 * k);
-            B[w0 + w] = v;
+            uint32_t x[4] = {0, 0, 0, 0};
+            for (int j = 0; j < 16; ++j)
+                if (lp + j < in_end) x[j >> 2] |= (uint32_t)lp[j] << (8 * (j & 3));
+            v = make_uint4(x[0], x[1], x[2], x[3]);
         }
+        uint32_t *d = B + d0 + 4 * k;
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
     }
     wave_sync();
     const bool ok = decode_inplace(B, base, base + len, ob);
