@@ -175,6 +175,22 @@ def gen_walk_int16(n: int, seed: int) -> np.ndarray:
     return (np.cumsum(steps) & 0xFFFF).astype(np.uint16).view(np.int16)
 
 
+def gen_short_matches(nbytes: int, seed: int, lit_max: int = 4, match_lo: int = 8,
+                      match_hi: int = 14, window: int = 600) -> np.ndarray:
+    """Bytes built as an LZ77 source: runs of 0..lit_max random literals, each
+    followed by a copy of match_lo..match_hi bytes from up to `window` bytes
+    back.  An 8 KiB block of it parses into hundreds of short sequences."""
+    rng = _rng(seed)
+    out = bytearray(rng.integers(0, 256, 16, dtype=np.uint8).tobytes())
+    while len(out) < nbytes:
+        out += rng.integers(0, 256, int(rng.integers(0, lit_max + 1)), dtype=np.uint8).tobytes()
+        ln = int(rng.integers(match_lo, match_hi + 1))
+        src = len(out) - int(rng.integers(1, min(window, len(out)) + 1))
+        for k in range(ln):  # byte by byte: overlapping copies repeat a period
+            out.append(out[src + k])
+    return np.frombuffer(bytes(out[:nbytes]), dtype=np.uint8).copy()
+
+
 def gen_chunk_bytes(spec: ChunkSpec, vis_inputs: int = 16) -> np.ndarray:
     """Raw (pre-rounding) chunk content as uint8 of exactly spec.nbytes.
 

@@ -185,6 +185,52 @@ def test_compress_parity(bsg, E, nb, n):
         assert np.array_equal(back[: n * E], data)
 
 
+def _lz4_sequence_count(block: bytes) -> int:
+    """Sequences in one LZ4 block (token walk only)."""
+    ip, n = 0, 0
+    while ip < len(block):
+        tok = block[ip]
+        ip += 1
+        ll = tok >> 4
+        if ll == 15:
+            while True:
+                ip += 1
+                ll += block[ip - 1]
+                if block[ip - 1] != 255:
+                    break
+        ip += ll
+        n += 1
+        if ip >= len(block):
+            break
+        ip += 2
+        if tok & 15 == 15:
+            while block[ip] == 255:
+                ip += 1
+            ip += 1
+    return n
+
+
+@pytest.mark.parametrize("E,nb", [(4, 2048), (1, 8192), (2, 4096)])
+def test_compress_many_sequences(bsg, E, nb):
+    """Blocks that parse into ~500 short sequences, so the encoder writes
+    them in several batches of 64 per block: the transposed domain holds an
+    LZ77-like source of short matches (synth.gen_short_matches), the input
+    is its inverse bit transpose."""
+    P = synth.gen_short_matches(nb * E * 3 + 500, 11 + E)
+    n = P.size // E
+    data = oracle.bitunshuffle(P[: n * E], E, nb)
+    ref = oracle.compress(data, E, nb)
+    nblk = int(np.frombuffer(ref[20:24].tobytes(), dtype="<u4")[0])
+    offs = np.frombuffer(ref[24:24 + 8 * (nblk + 1)].tobytes(), dtype="<u8")
+    pay = ref[24 + 8 * (nblk + 1):].tobytes()
+    counts = [_lz4_sequence_count(pay[offs[i]:offs[i + 1]]) for i in range(nblk)]
+    assert max(counts) > 3 * 64, counts
+    got = host(bsg.compress_sync(dev(data), E, nb))
+    assert got.size == ref.size and np.array_equal(got, ref)
+    back = host(bsg.decompress_sync(dev(ref), n, E, nb))
+    assert np.array_equal(back[: n * E], data)
+
+
 def test_pipeline_config0(bsg):
     """Tiny plain pipeline: (16, 36, 64) complex64, f = 0.01, 8 KiB blocks."""
     vis, autos = synth.gen_vis(16, 8, 64, 0, N)

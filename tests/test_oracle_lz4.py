@@ -258,3 +258,42 @@ def test_threads_do_not_change_bytes(oracle_lib):
     a = oracle_lib.compress(r, 4, 2048, nthreads=1)
     b = oracle_lib.compress(r, 4, 2048, nthreads=5)
     assert np.array_equal(a, b)
+
+
+def test_short_match_source_parses_into_many_sequences():
+    """The short-match generator (used by the GPU many-sequence parity test)
+    really yields hundreds of sequences per block once placed in the
+    transposed domain, and the oracle stream round-trips."""
+    import oracle
+    E, nb = 4, 2048
+    P = synth.gen_short_matches(nb * E * 2, 15)
+    data = oracle.bitunshuffle(P, E, nb)
+    assert np.array_equal(oracle.bitshuffle(data, E, nb), P)
+    s = oracle.compress(data, E, nb)
+    nblk = int(np.frombuffer(s[20:24].tobytes(), dtype="<u4")[0])
+    offs = np.frombuffer(s[24:24 + 8 * (nblk + 1)].tobytes(), dtype="<u8")
+    pay = s[24 + 8 * (nblk + 1):].tobytes()
+    n_seq = 0
+    blk = pay[offs[0]:offs[1]]
+    ip = 0
+    while ip < len(blk):  # token walk of the first block
+        tok = blk[ip]
+        ip += 1
+        ll = tok >> 4
+        if ll == 15:
+            while blk[ip] == 255:
+                ll += 255
+                ip += 1
+            ll += blk[ip]
+            ip += 1
+        ip += ll
+        n_seq += 1
+        if ip >= len(blk):
+            break
+        ip += 2
+        if tok & 15 == 15:
+            while blk[ip] == 255:
+                ip += 1
+            ip += 1
+    assert n_seq > 3 * 64
+    assert np.array_equal(oracle.decompress(s, data.size // E, E, nb), data)
