@@ -236,11 +236,23 @@ __device__ __forceinline__ int emit_sequences(uint8_t *__restrict__ dst, int op,
     const uint32_t mrem = (uint32_t)(mlc - 15 - 255 * (mext - 1));
     const int tpos = start + hsz + ll;
     const int fmax = act ? (hsz > tsz ? hsz : tsz) : 0;
-    for (int k = 0; __ballot(k < fmax) != 0; ++k) {
+    constexpr int kShort = 4; // field bytes each lane writes itself
+    for (int k = 0; k < kShort && __ballot(k < fmax) != 0; ++k) {
         if (act && k < hsz) dst[start + k] = (uint8_t)(k == 0 ? tok : (k < lext ? 255u : lrem));
         if (act && k < tsz)
             dst[tpos + k] = (uint8_t)(k == 0 ? (uint32_t)off & 255u
                                              : (k == 1 ? (uint32_t)off >> 8 : (k < tsz - 1 ? 255u : mrem)));
+    }
+    // the rest of a long length field (a run of 255s, then the remainder):
+    // the wave writes one such sequence at a time
+    for (uint64_t longs = __ballot(fmax > kShort); longs; longs &= longs - 1) {
+        const int j = __builtin_ctzll(longs);
+        const int st_j = __builtin_amdgcn_readlane(start, j), h_j = __builtin_amdgcn_readlane(hsz, j);
+        const int tp_j = __builtin_amdgcn_readlane(tpos, j), t_j = __builtin_amdgcn_readlane(tsz, j);
+        const uint32_t lr_j = (uint32_t)__builtin_amdgcn_readlane((int)lrem, j);
+        const uint32_t mr_j = (uint32_t)__builtin_amdgcn_readlane((int)mrem, j);
+        for (int k = kShort + lane; k < h_j; k += kWave) dst[st_j + k] = (uint8_t)(k < h_j - 1 ? 255u : lr_j);
+        for (int k = kShort + lane; k < t_j; k += kWave) dst[tp_j + k] = (uint8_t)(k < t_j - 1 ? 255u : mr_j);
     }
 
     // literal runs: task t of the wave is the 16 output bytes (ls_j / 16) +
