@@ -550,11 +550,13 @@ __device__ __forceinline__ uint32_t range_mask(int d, int op, int end)
     return mhi & ~((1u << (8 * lo)) - 1u);
 }
 
-__device__ __forceinline__ void put_word(uint32_t *b32, int w, uint32_t v, int op, int end)
+// (every lane reads its destination dword together with its sources, so a
+// partial dword costs no second round trip and no branch)
+__device__ __forceinline__ void put_word(uint32_t *b32, int w, uint32_t v, uint32_t old, int op,
+                                         int end)
 {
     const uint32_t m = range_mask(4 * w, op, end);
-    if (m != 0xFFFFFFFFu) v = (v & m) | (b32[w] & ~m);
-    b32[w] = v;
+    b32[w] = (v & m) | (old & ~m);
 }
 
 // out[op, op + len) = buf[src, src + len) for src >= op (literals: every step
@@ -569,7 +571,8 @@ __device__ __forceinline__ void dcopy(uint32_t *b32, int op, int src, int len)
         const int w = b + (int)threadIdx.x;
         if (w < w1) {
             const int a = (4 * w + delta) >> 2;
-            put_word(b32, w, __builtin_amdgcn_alignbyte(b32[a + 1], b32[a], sh), op, end);
+            const uint32_t old = b32[w];
+            put_word(b32, w, __builtin_amdgcn_alignbyte(b32[a + 1], b32[a], sh), old, op, end);
         }
     }
 }
@@ -595,6 +598,7 @@ __device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
         for (int b = w0; b < w1; b += kWave) {
             const int w = b + (int)threadIdx.x;
             if (w < w1) {
+                const uint32_t old = b32[w];
                 uint32_t v;
                 if (off == 1) {
                     v = p0 * 0x01010101u;
@@ -606,7 +610,7 @@ __device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
                     const uint32_t c2 = r == 0 ? p2 : (r == 1 ? p0 : p1);
                     v = a | (c1 << 8) | (c2 << 16) | (a << 24);
                 }
-                put_word(b32, w, v, op, end);
+                put_word(b32, w, v, old, op, end);
             }
             r += step;
             if (r >= off) r -= off;
@@ -616,6 +620,7 @@ __device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
     for (int b = w0; b < w1; b += kWave) {
         const int w = b + (int)threadIdx.x;
         if (w < w1) {
+            const uint32_t old = b32[w];
             uint32_t v;
             if (r + 3 < off) {
                 const int sidx = base + r;
@@ -628,7 +633,7 @@ __device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
                     v |= (uint32_t)b8[base + rj] << (8 * j);
                 }
             }
-            put_word(b32, w, v, op, end);
+            put_word(b32, w, v, old, op, end);
         }
         r += step;
         if (r >= off) r -= off;
