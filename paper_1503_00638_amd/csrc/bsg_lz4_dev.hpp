@@ -617,22 +617,19 @@ __device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
         }
         return;
     }
+    const uint32_t head = __builtin_amdgcn_alignbyte(b32[(base >> 2) + 1], b32[base >> 2],
+                                                     (uint32_t)(base & 3));
     for (int b = w0; b < w1; b += kWave) {
         const int w = b + (int)threadIdx.x;
         if (w < w1) {
             const uint32_t old = b32[w];
-            uint32_t v;
-            if (r + 3 < off) {
-                const int sidx = base + r;
-                v = __builtin_amdgcn_alignbyte(b32[(sidx >> 2) + 1], b32[sidx >> 2],
-                                               (uint32_t)(sidx & 3));
-            } else {
-                v = 0;
-                for (int j = 0; j < 4; ++j) {
-                    const int rj = r + j < off ? r + j : r + j - off;
-                    v |= (uint32_t)b8[base + rj] << (8 * j);
-                }
-            }
+            // 4 bytes of the period from r; where they run past its end
+            // (k = off - r < 4 of them), the rest comes from its start
+            const int sidx = base + r;
+            uint32_t v = __builtin_amdgcn_alignbyte(b32[(sidx >> 2) + 1], b32[sidx >> 2],
+                                                    (uint32_t)(sidx & 3));
+            const int k = off - r;
+            if (k < 4) v = (v & ((1u << (8 * k)) - 1u)) | (head << (8 * k));
             put_word(b32, w, v, old, op, end);
         }
         r += step;
