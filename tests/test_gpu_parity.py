@@ -287,6 +287,36 @@ def test_decode_liblz4_payloads(bsg):
         assert np.array_equal(got, expect)
 
 
+def test_decode_overlapping_periods(bsg):
+    """Overlapping matches of every small period: blocks holding a random
+    pattern of period 1..20 after 0..3 random bytes, encoded by the system
+    liblz4, so the decoder replicates periods shorter and longer than a
+    dword at every byte phase."""
+    if not lz4ref.available():
+        pytest.skip("no liblz4")
+    E, nb = 4, 2048
+    rng = np.random.default_rng(21)
+    blocks = []
+    for p in range(1, 21):
+        lead = p % 4
+        pat = rng.integers(0, 256, p, dtype=np.uint8)
+        body = np.resize(pat, nb * E - lead)
+        blocks.append(rng.integers(0, 256, lead, dtype=np.uint8).tobytes() + body.tobytes())
+    nblk = len(blocks)
+    data_sh = b"".join(blocks)
+    for enc in (lz4ref.compress_default, lz4ref.compress_hc):
+        pays = [enc(b) for b in blocks]
+        off = np.zeros(nblk + 1, dtype=np.uint64)
+        off[1:] = np.cumsum([len(q) for q in pays])
+        hdr = np.array([0x31475342, E], dtype=np.uint32).tobytes() + \
+            np.array([nblk * nb], dtype=np.uint64).tobytes() + \
+            np.array([nb, nblk], dtype=np.uint32).tobytes()
+        stream = np.frombuffer(hdr + off.tobytes() + b"".join(pays), dtype=np.uint8)
+        expect = oracle.bitunshuffle(np.frombuffer(data_sh, np.uint8), E, nb)
+        got = host(bsg.decompress_sync(dev(stream), nblk * nb, E, nb))
+        assert np.array_equal(got, expect)
+
+
 def test_decode_rejects_corruption(bsg):
     E, nb = 4, 2048
     x = synth.gen_gauss_int32(2048 * 8 + 5, 6, 2)
