@@ -394,7 +394,7 @@ __device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table,
         // serialised.  The next lane's value comes from a DPP wave shift
         // (lane i reads lane i + 1).  A lane with nothing to insert takes a
         // max with 0 at an entry of its own: no effect, no branch.
-        const uint32_t vn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppWaveShl1, 0xF, 0xF, false);
+        const uint32_t vn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppWaveShl1, 0xF, 0xF, true);
         const bool run_on = lane != kWave - 1 && (FULL || p + 1 <= last_ins) && vn == v;
         const uint32_t val = ins && !run_on ? (uint32_t)(p + 1) : 0u;
         atomicMax(&table[val != 0 ? h : (uint32_t)lane], val);
