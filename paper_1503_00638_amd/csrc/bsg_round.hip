@@ -8,9 +8,9 @@
 //   tie-breaking footnote of Section 3.2); Im of an auto carries no noise
 //   and is left alone.
 //
-// The rounding is done on the float32 bit pattern with integer arithmetic
-// (round-half-even on the magnitude bits), the exponent k of g is read off
-// the bits of the double G2: no log, sqrt or division.
+// The value is scaled by 2^-k in double, rounded half to even there and
+// scaled back (both scalings exact); k comes from the exponent and mantissa
+// of the double G2 (frexp): no log, sqrt or division.
 #include "bsg_internal.hpp"
 #include "bsg_round_dev.hpp"
 
@@ -18,15 +18,11 @@ namespace bsg {
 
 namespace {
 
-constexpr int kComplexPerThread = 8;
+constexpr int kComplexPerThread = 4;
 
-// A wavefront rounds 512 consecutive visibilities; lane l takes elements
-// l, l + 64, ..., l + 448 of them, so every load and store instruction of the
-// wave touches 512 contiguous bytes.  The position (time, product, inputs,
-// auto rows) is found once per lane and then stepped.
 // Lane i of the grid rounds the kComplexPerThread consecutive visibilities
 // from e0 = i * kComplexPerThread.  When they lie in one product row at one
-// frequency (times t .. t + 7, the case whenever T is a multiple of 8), the
+// frequency (times t .. t + 3, the case whenever T is a multiple of 4), the
 // values and their autos are read with 16-byte loads from one base each and
 // every value is rounded without a branch; otherwise a cursor steps through
 // them one by one.
@@ -83,20 +79,50 @@ __global__ __launch_bounds__(256) void k_round(const float2 *__restrict__ vin,
     }
 }
 
+// As k_round, for int32 visibilities and autos (exact int64 products).
 __global__ __launch_bounds__(256) void k_round_i32(const int2 *__restrict__ vin,
                                                    int2 *__restrict__ vout, RoundParams rp,
-                                                   int64_t n_complex)
+                                                   int64_t n_complex, int aligned16)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    int64_t e = wave * (kWave * kComplexPerThread) + lane;
-    if (e >= n_complex) return;
-    VisCursor c = cursor_at(rp, e);
-    for (int k = 0;;) {
-        vout[e] = round_at_i32(vin[e], c, rp);
-        e += kWave;
-        if (++k == kComplexPerThread || e >= n_complex) break;
-        cursor_advance(rp, c, kWave);
+    constexpr int K = kComplexPerThread;
+    const int64_t e0 = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * K;
+    if (e0 >= n_complex) return;
+    VisCursor c = cursor_at(rp, e0);
+    if (aligned16 && e0 + K <= n_complex && c.t + K <= rp.T) {
+        const int4 *v4 = reinterpret_cast<const int4 *>(vin + e0);
+        int4 v[K / 2];
+#pragma unroll
+        for (int k = 0; k < K / 2; ++k) v[k] = v4[k];
+        const int32_t *pi = rp.autos_i32 + c.row_i + c.t;
+        const int32_t *pj = rp.autos_i32 + c.row_j + c.t;
+        int64_t ai[K], aj[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            ai[k] = pi[k];
+            aj[k] = pj[k];
+        }
+        const bool is_auto = c.i == c.j;
+        int4 *o4 = reinterpret_cast<int4 *>(vout + e0);
+#pragma unroll
+        for (int k = 0; k < K / 2; ++k) {
+            int32_t x[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j = 2 * k + h;
+                const double G2 = (double)(ai[j] * aj[j]) * (is_auto ? rp.c_auto : rp.c);
+                if (G2 > 0.0 && G2 != __builtin_inf()) {
+                    const int kk = granularity_k(G2);
+                    x[2 * h] = round_int(x[2 * h], kk);
+                    if (!is_auto) x[2 * h + 1] = round_int(x[2 * h + 1], kk);
+                }
+            }
+            o4[k] = make_int4(x[0], x[1], x[2], x[3]);
+        }
+        return;
+    }
+    for (int k = 0; k < K && e0 + k < n_complex; ++k) {
+        if (k) cursor_advance(rp, c, 1);
+        vout[e0 + k] = round_at_i32(vin[e0 + k], c, rp);
     }
 }
 
@@ -161,9 +187,10 @@ hipError_t launch_round_i32(const int32_t *vin, int32_t *vout, const RoundParams
     if (n_complex == 0) return hipSuccess;
     const int64_t waves = (n_complex + kWave * kComplexPerThread - 1) / (kWave * kComplexPerThread);
     const int64_t blocks = (waves * kWave + 255) / 256;
+    const int aligned16 = (((uintptr_t)vin | (uintptr_t)vout) & 15) == 0;
     hipLaunchKernelGGL(k_round_i32, dim3((unsigned)blocks), dim3(256), 0, s,
                        reinterpret_cast<const int2 *>(vin), reinterpret_cast<int2 *>(vout), rp,
-                       n_complex);
+                       n_complex, aligned16);
     return hipGetLastError();
 }
 
