@@ -23,7 +23,7 @@ def bsg():
 
 
 def dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    return torch.from_numpy(np.array(a, copy=True, order="C")).to("cuda:0")
 
 
 def host(t):
