@@ -166,6 +166,58 @@ __global__ __launch_bounds__(256) void k_noise_comp(const float2 *__restrict__ v
     }
 }
 
+// T a power of two up to 1024: one workgroup of 1024 threads per frequency.
+// Thread k takes time t = k mod T and the products p = k / T, k / T + R, ...
+// (R = 1024 / T), so each step of the workgroup reads 8 KiB of the
+// contiguous [P][T] block of that frequency; the thread's inputs (i, j) are
+// stepped along with p.  The per-thread minima are then reduced over the R
+// threads of each time in LDS.  The minimum does not depend on the order of
+// the terms (no term is -0, NaN terms are skipped).
+constexpr int kCompThreads = 1024;
+
+__global__ __launch_bounds__(kCompThreads) void k_noise_comp_rows(const float2 *__restrict__ vis,
+                                                                 RoundParams rp,
+                                                                 double *__restrict__ scale)
+{
+    __shared__ double part[kCompThreads];
+    const int k = threadIdx.x;
+    const int T = (int)rp.T, R = kCompThreads / T;
+    const int t = k & (T - 1), r = k / T;
+    const int64_t fr = blockIdx.x;
+    const float2 *vrow = vis + fr * rp.P * rp.T + t;
+    const float *arow = rp.autos + fr * rp.I * rp.T + t;
+    double m = 1.0;
+    int32_t i = 0, j = 0;
+    if (r < rp.P) product_pair(rp, r, i, j);
+#pragma unroll 4
+    for (int64_t p = r; p < rp.P; p += R) {
+        const float2 v = vrow[p * T];
+        const double ab = (double)arow[(int64_t)i * T] * (double)arow[(int64_t)j * T];
+        const double term = 1.0 - ((double)v.x * (double)v.x + (double)v.y * (double)v.y) / ab;
+        if (i != j && ab > 0.0 && ab != __builtin_inf() && term < m) m = term; // a NaN term never wins
+        // the inputs of product p + R
+        if (rp.prod_map) {
+            if (p + R < rp.P) {
+                i = rp.prod_map[2 * (p + R)];
+                j = rp.prod_map[2 * (p + R) + 1];
+            }
+        } else {
+            j += R;
+            while (j >= rp.I && i < rp.I) {
+                j += i + 1 - (int32_t)rp.I; // the next row starts at j = i + 1
+                ++i;
+            }
+        }
+    }
+    part[k] = m;
+    __syncthreads();
+    for (int st = R / 2; st >= 1; st >>= 1) {
+        if (r < st && part[k + st * T] < part[k]) part[k] = part[k + st * T];
+        __syncthreads();
+    }
+    if (r == 0) scale[fr * T + t] = part[t];
+}
+
 } // namespace
 
 hipError_t launch_round(const float *vin, float *vout, const RoundParams &rp, hipStream_t s)
@@ -197,6 +249,11 @@ hipError_t launch_round_i32(const int32_t *vin, int32_t *vout, const RoundParams
 hipError_t launch_noise_comp(const float *vis, const RoundParams &rp, double *scale, hipStream_t s)
 {
     if (rp.F * rp.T == 0) return hipSuccess;
+    if (rp.T <= kCompThreads && (rp.T & (rp.T - 1)) == 0) {
+        hipLaunchKernelGGL(k_noise_comp_rows, dim3((unsigned)rp.F), dim3(kCompThreads), 0, s,
+                           reinterpret_cast<const float2 *>(vis), rp, scale);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)rp.F, (unsigned)((rp.T + kWave - 1) / kWave));
     hipLaunchKernelGGL(k_noise_comp, grid, dim3(256), 0, s, reinterpret_cast<const float2 *>(vis),
                        rp, scale);

@@ -31,8 +31,12 @@ def host(t):
     return t.cpu().numpy()
 
 
+# T a power of two up to 1024 takes the one-workgroup-per-frequency kernel
+# (including steps of the product index that wrap several rows of inputs:
+# T = 2 with 40 inputs), other T the per-time kernel.
 CASES = [(4, 8, 64, 0, 0.4), (3, 5, 7, 1, 0.0), (2, 16, 130, 2, 2.0), (1, 1, 5, 3, 0.4),
-         (2, 2, 65, 4, 1.0), (5, 3, 1, 5, 0.4), (16, 8, 64, 6, 0.1)]
+         (2, 2, 65, 4, 1.0), (5, 3, 1, 5, 0.4), (16, 8, 64, 6, 0.1), (2, 40, 2, 7, 0.4),
+         (1, 4, 1024, 8, 0.4), (3, 13, 32, 9, 0.0)]
 
 
 @pytest.mark.parametrize("F,I,T,seed,source", CASES)
@@ -57,8 +61,9 @@ def test_compensated_rounding_parity(bsg, F, I, T, seed, source):
     assert np.array_equal(got.view(np.uint32), oracle.round_to_noise_scaled(vis, autos, N, 0.01, m).view(np.uint32))
 
 
-def test_compensation_degenerate_inputs(bsg):
-    vis, autos = synth.gen_vis_point_source(3, 6, 40, 9, 0.4)
+@pytest.mark.parametrize("T", [40, 32])
+def test_compensation_degenerate_inputs(bsg, T):
+    vis, autos = synth.gen_vis_point_source(3, 6, T, 9, 0.4)
     autos[0, 1, :5] = [0.0, -3.0, np.nan, np.inf, 1e-40]
     autos[1, :, 7] = 0.0
     vis.view(np.float32).reshape(-1)[::17] = np.nan
