@@ -6,6 +6,10 @@ benchmark times.
   compressed stream equal the oracle's (the oracle runs multi-threaded over
   blocks, as in the paper's threading model), and the decompressed bytes
   equal the rounded input.
+* The same chunk through the byte-shuffle comparator; integer visibilities
+  (int32 re/im) rounded and compressed as 8-byte elements; the compensated
+  diagonal model on a point-source-dominated chunk; full-covariance
+  rounding for small arrays on sampled frequencies.
 * Bit-transpose sweep, 1 GiB at elem_size 1/2/4/8/16 and block sizes of
   2048/8192/65536 bytes: the round trip is the identity on the whole buffer
   and sampled blocks (first, last, random) equal the oracle's transpose.
@@ -142,3 +146,81 @@ def test_batch_4096_chunks_full(bsg):
         ref = oracle.compress(raw, s.elem_size, 8192 // s.elem_size)
         assert nb[k] == ref.size, s
         assert np.array_equal(plan.outs[k][: ref.size].cpu().numpy(), ref), s
+
+
+def test_chime_chunk_byte_filter_full(bsg, chime):
+    """The comparator filter (byte shuffle before the same LZ4) on the rounded
+    full chunk at 8192-byte blocks: the stream equals the oracle's and
+    decodes back to the rounded input."""
+    vis, autos = chime
+    r = oracle.round_to_noise(vis, autos, N, F_FRAC)
+    ref = oracle.compress(r, 4, 2048, filter=1)
+    x = torch.from_numpy(r.view(np.uint8).reshape(-1)).cuda()
+    out, nb = bsg.compress(x, 4, 2048, filter=bsg.BSG_FILTER_BYTE)
+    torch.cuda.synchronize()
+    m = int(nb.item())
+    assert m == ref.size
+    assert np.array_equal(out[:m].cpu().numpy(), ref)
+    dec, st = bsg.decompress(out, m, r.size * 2, 4, 2048, filter=bsg.BSG_FILTER_BYTE)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and torch.equal(dec.view(torch.uint8), x)
+
+
+def test_integer_chunk_full(bsg):
+    """Integer visibilities (int32 re/im, the model scaled by 1024) at the
+    CHIME-Pathfinder shape: the rounded values equal the oracle's, the
+    stream of 8-byte elements in 8192-byte blocks equals the oracle's, and
+    it decodes back to the rounded values."""
+    vis, autos = synth.gen_vis_int(1024, 128, 32, 1, N)
+    r = oracle.round_to_noise_i32(vis, autos, N, F_FRAC)
+    got = bsg.round_to_noise_i32(torch.from_numpy(vis).cuda(), torch.from_numpy(autos).cuda(),
+                                 N, F_FRAC)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), r)
+    del vis, autos
+    flat = got.view(torch.uint8).reshape(-1)
+    ref = oracle.compress(r, 8, 1024)
+    out, nb = bsg.compress(flat, 8, 1024)
+    torch.cuda.synchronize()
+    m = int(nb.item())
+    assert m == ref.size
+    assert np.array_equal(out[:m].cpu().numpy(), ref)
+    dec, st = bsg.decompress(out, m, r.size // 2, 8, 1024)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0 and torch.equal(dec.view(torch.uint8), flat)
+
+
+def test_compensation_full(bsg):
+    """The compensated diagonal model (Section 3.2) at the CHIME-Pathfinder
+    shape on visibilities dominated by a point source (40 % of the receiver
+    power in every product): the (F, T) factor and the rounding that uses
+    it equal the oracle's, in the one-workgroup-per-frequency launch."""
+    vis, autos = synth.gen_vis_point_source(1024, 128, 32, 1, 0.4, N)
+    fac = oracle.noise_compensation(vis, autos)
+    dv, da = torch.from_numpy(vis).cuda(), torch.from_numpy(autos).cuda()
+    gfac = bsg.noise_compensation(dv, da)
+    torch.cuda.synchronize()
+    assert np.array_equal(gfac.cpu().numpy().view(np.uint64), fac.view(np.uint64))
+    assert fac.min() < 1.0
+    ref = oracle.round_to_noise_scaled(vis, autos, N, F_FRAC, fac)
+    got = bsg.round_to_noise_scaled(dv, da, N, F_FRAC, gfac)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("I,F,T", [(8, 1024, 64), (11, 256, 64)])
+def test_fullcov_sampled_frequencies(bsg, I, F, T):
+    """Full-covariance rounding (Section 3.2) at the small-array shapes the
+    benchmark times: the whole array is rounded on the device in one
+    launch, and sampled frequencies (first, last, two random) equal the
+    oracle's rounding of those frequencies, each sample being independent
+    of the others."""
+    vis, autos = synth.gen_vis(F, I, T, 1, N)
+    got = bsg.round_to_noise_fullcov(torch.from_numpy(vis).cuda(), torch.from_numpy(autos).cuda(),
+                                     N, F_FRAC)
+    torch.cuda.synchronize()
+    g = got.cpu().numpy()
+    rng = np.random.default_rng(I * 1000 + F)
+    for fi in sorted({0, F - 1, *rng.integers(0, F, 2).tolist()}):
+        ref = oracle.round_to_noise_fullcov(vis[fi:fi + 1], autos[fi:fi + 1], N, F_FRAC)
+        assert np.array_equal(g[fi:fi + 1].view(np.uint32), ref.view(np.uint32)), fi
