@@ -353,30 +353,32 @@ __device__ __forceinline__ int extend_match(const uint32_t *b32, int c, int q, i
 }
 
 // b32: block bytes (n <= MAXB) followed by >= 12 readable padding bytes.
-// Per group of 512 positions: (1) read 8 bytes at every position, (2) per
-// 64-position chunk read the table entry of every position, then raise the
-// entries to the chunk's positions (the wave's in-order LDS queue makes chunk
-// c see exactly chunks < c), (3) verify 8 bytes at every candidate, (4) parse
-// greedily with the candidate words in VGPRs and the match masks in SGPRs.
+// Per group of 512 positions: (1) read the 4 bytes at every position, (2)
+// per 64-position chunk read the table entry of every position, then raise
+// the entries to the chunk's positions (the wave's in-order LDS queue makes
+// chunk c see exactly chunks < c), (3) verify 8 bytes at every candidate of
+// a chunk the parse enters, (4) parse greedily with the candidates in VGPRs
+// and the match masks in SGPRs.
 // Hash and insert the kGroup positions from g0 (the fixed rule of the LZ4
-// stage): per chunk cc of 64 positions, v/v2 hold bytes p..p+3 / p+4..p+7
-// of each lane's position p and cand the table entry it found (position +
-// 1, 0 = none) before the chunk's own inserts.  FULL: the whole group lies
-// at or below last_take, so the bound checks drop out.
+// stage): per chunk cc of 64 positions, cand holds the table entry (position
+// + 1, 0 = none) each lane's position found before the chunk's own inserts.
+// FULL: the whole group lies at or below last_take, so the bound checks drop
+// out, and as g0 is a multiple of 4 every chunk's loads share one base with
+// immediate offsets.
 template <int MAXB, bool FULL>
 __device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table, int g0, int last_q,
-                                           int last_ins, u32x16 &vv, u32x16 &candv)
+                                           int last_ins, u32x16 &candv)
 {
     constexpr int NC = kGroup / kChunk;
     const int lane = threadIdx.x;
+    uint32_t vv[NC];
+    const uint32_t *dg = b32 + ((g0 + lane) >> 2);
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
         const int p = g0 + cc * kChunk + lane;
         const int pc = FULL || p < MAXB ? p : MAXB;
-        const uint32_t *d = b32 + (pc >> 2);
-        const uint32_t d0 = d[0], d1 = d[1], d2 = d[2];
-        vv[cc] = __builtin_amdgcn_alignbyte(d1, d0, (uint32_t)(pc & 3));
-        vv[cc + NC] = __builtin_amdgcn_alignbyte(d2, d1, (uint32_t)(pc & 3));
+        const uint32_t *d = FULL ? dg + cc * (kChunk / 4) : b32 + (pc >> 2);
+        vv[cc] = __builtin_amdgcn_alignbyte(d[1], d[0], (uint32_t)(pc & 3));
     }
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) {
@@ -384,7 +386,6 @@ __device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table,
         const int c0 = g0 + cc * kChunk;
         const int p = c0 + lane;
         const uint32_t v = vv[cc];
-        const bool ins = FULL || p <= last_ins;
         const uint32_t h = (v * kHashMult) >> (32 - kHashBits);
         const uint32_t t = table[h];
         candv[cc] = FULL || p <= last_q ? t : 0u;
@@ -392,29 +393,34 @@ __device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table,
         // run's last position writes: the entry takes the largest position
         // either way, and atomics of many lanes on one address would be
         // serialised.  The next lane's value comes from a DPP wave shift
-        // (lane i reads lane i + 1).  A lane with nothing to insert takes a
-        // max with 0 at an entry of its own: no effect, no branch.
+        // (lane i reads lane i + 1).  The other lanes are masked off.
         const uint32_t vn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppWaveShl1, 0xF, 0xF, true);
         const bool run_on = lane != kWave - 1 && (FULL || p + 1 <= last_ins) && vn == v;
-        const uint32_t val = ins && !run_on ? (uint32_t)(p + 1) : 0u;
-        atomicMax(&table[val != 0 ? h : (uint32_t)lane], val);
+        if ((FULL || p <= last_ins) && !run_on)
+            atomicMax(&table[h], (uint32_t)(p + 1));
     }
 }
 
-// The mask of the chunk's positions (from c0) whose candidate matches for
-// 8 bytes and may be taken (<= last_take).  Branch-free: a lane without a
-// candidate reads position 0 and is masked after.
-__device__ __forceinline__ uint64_t verify_chunk(const uint32_t *b32, int c0, uint32_t v, uint32_t v2,
-                                                 uint32_t cand, int last_take)
+// The mask of the chunk's positions (from c0, a multiple of 64) whose
+// candidate matches for 8 bytes and may be taken (<= last_take).
+// Branch-free: a lane without a candidate reads position 0 and is masked
+// after.
+__device__ __forceinline__ uint64_t verify_chunk(const uint32_t *b32, int c0, uint32_t cand,
+                                                 int last_take)
 {
     const int p = c0 + (int)threadIdx.x;
     const uint32_t cn = c0 + kChunk - 1 <= last_take || p <= last_take ? cand : 0u;
     const int c = cn != 0 ? (int)cn - 1 : 0;
+    const uint32_t *o = b32 + (p >> 2);
     const uint32_t *d = b32 + (c >> 2);
+    const uint32_t o0 = o[0], o1 = o[1], o2 = o[2];
     const uint32_t e0 = d[0], e1 = d[1], e2 = d[2];
     // zero when the candidate exists and its 8 bytes equal those at p
-    const uint32_t x = (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) ^ v) |
-                       (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) ^ v2) | ((cn - 1u) >> 31);
+    const uint32_t x = (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) ^
+                        __builtin_amdgcn_alignbyte(o1, o0, (uint32_t)(p & 3))) |
+                       (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) ^
+                        __builtin_amdgcn_alignbyte(o2, o1, (uint32_t)(p & 3))) |
+                       ((cn - 1u) >> 31);
     return __ballot(x == 0);
 }
 
@@ -423,14 +429,14 @@ __device__ __forceinline__ uint64_t verify_chunk(const uint32_t *b32, int c0, ui
 // hashed and inserted a group of 8 chunks at a time; a chunk's candidates
 // are verified only when the parse reaches it, so chunks inside a long
 // match are never verified.  Sequences are written 64 at a time.
-// (Per-chunk values sit in 16-wide register vectors: a uniform index into
-// one compiles to a relative register move.)
+// (The group's candidates sit in a 16-wide register vector: a uniform index
+// into one compiles to a relative register move.)
 template <int MAXB>
 __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t *table,
                                             uint8_t *__restrict__ dst)
 {
     constexpr int NC = kGroup / kChunk;
-    static_assert(2 * NC <= 16, "v and v2 of a group share one vector");
+    static_assert(NC <= 16, "a group's candidates fit one vector");
     const int lane = threadIdx.x;
     for (int i = lane; i < (1 << kHashBits) / 4; i += kWave)
         reinterpret_cast<uint4 *>(table)[i] = make_uint4(0, 0, 0, 0);
@@ -443,19 +449,19 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
     // sequences found and not yet written: lane j holds sequence j
     int ns = 0, s_lit = 0, s_ll = 0, s_off = 0, s_ml = 0;
     for (int g0 = 0; g0 <= last_q; g0 += kGroup) {
-        u32x16 vv, candv;
+        u32x16 candv;
         // a group whose every position (and the one after it) may be
         // inserted, looked up and taken needs no bound checks
         if (g0 + kGroup <= last_take)
-            hash_group<MAXB, true>(b32, table, g0, last_q, last_ins, vv, candv);
+            hash_group<MAXB, true>(b32, table, g0, last_q, last_ins, candv);
         else
-            hash_group<MAXB, false>(b32, table, g0, last_q, last_ins, vv, candv);
+            hash_group<MAXB, false>(b32, table, g0, last_q, last_ins, candv);
 
         // chunk by chunk from the one holding the parse position
         for (int cc = (pnext > g0 ? pnext - g0 : 0) >> 6; cc < NC; ++cc) {
             const int c0 = g0 + cc * kChunk;
             if (c0 > last_take) break;
-            const uint64_t mk = verify_chunk(b32, c0, vv[cc], vv[cc + NC], candv[cc], last_take);
+            const uint64_t mk = verify_chunk(b32, c0, candv[cc], last_take);
             for (;;) {
                 const int rel = pnext - c0;
                 const uint64_t mm = rel > 0 ? mk & (~0ull << rel) : mk;
