@@ -596,8 +596,17 @@ __device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
     const uint8_t *b8 = reinterpret_cast<const uint8_t *>(b32);
     const int w0 = op >> 2, w1 = (op + len + 3) >> 2, end = op + len;
     const int base = op - off;
-    int r = (4 * (w0 + (int)threadIdx.x) - op + 4 * off) % off;
-    const int step = (4 * kWave) % off;
+    // Remainders by off without a division: with M = 2^32 / off rounded up
+    // by less than 2^24 / off (an upward-biased hardware reciprocal is well
+    // inside that), floor(x M / 2^32) = floor(x / off) for 0 <= x <= 256.
+    // The lane's byte offset x = 4 (w0 + lane) - op lies in [-3, 252]; a
+    // negative one (lane 0) is below off, so one or two periods lift it.
+    // (For off = 1 the value is not used.)
+    const uint32_t M = (uint32_t)__builtin_amdgcn_readfirstlane(
+                           (int)(uint32_t)(__builtin_amdgcn_rcpf((float)off) * 4294971392.0f)) + 1u;
+    const int x = 4 * (w0 + (int)threadIdx.x) - op;
+    int r = x >= 0 ? x - off * (int)__umulhi((uint32_t)x, M) : (x + off >= 0 ? x + off : x + 2 * off);
+    const int step = 4 * kWave - off * (int)__umulhi(4u * kWave, M);
     if (off < 4) { // a period of 1..3 bytes, replicated from registers
         const uint32_t p0 = b8[base], p1 = b8[base + (off > 1 ? 1 : 0)],
                        p2 = b8[base + (off > 2 ? 2 : 0)];

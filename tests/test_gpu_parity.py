@@ -317,6 +317,38 @@ def test_decode_overlapping_periods(bsg):
         assert np.array_equal(got, expect)
 
 
+def test_decode_long_overlapping_periods(bsg):
+    """Overlapping matches with long periods in 64 KiB blocks (offsets up to
+    40000, every byte phase of the period start), encoded by the oracle and,
+    when present, by the system liblz4: the decoder's per-lane position in
+    the period and its advance per step are exact for large offsets."""
+    E, nb = 4, 16384
+    rng = np.random.default_rng(22)
+    periods = [21, 63, 64, 65, 255, 256, 257, 1021, 4093, 8192, 8193, 20000, 32767, 40000]
+    blocks = []
+    for k, p in enumerate(periods):
+        lead = k % 4
+        pat = rng.integers(0, 256, p, dtype=np.uint8)
+        body = np.resize(pat, nb * E - lead)
+        blocks.append(rng.integers(0, 256, lead, dtype=np.uint8).tobytes() + body.tobytes())
+    nblk = len(blocks)
+    data_sh = b"".join(blocks)
+    expect = oracle.bitunshuffle(np.frombuffer(data_sh, np.uint8), E, nb)
+    encoders = [lambda b: oracle.lz4_compress_block(np.frombuffer(b, np.uint8))]
+    if lz4ref.available():
+        encoders += [lz4ref.compress_default, lz4ref.compress_hc]
+    for enc in encoders:
+        pays = [enc(b) for b in blocks]
+        off = np.zeros(nblk + 1, dtype=np.uint64)
+        off[1:] = np.cumsum([len(q) for q in pays])
+        hdr = np.array([0x31475342, E], dtype=np.uint32).tobytes() + \
+            np.array([nblk * nb], dtype=np.uint64).tobytes() + \
+            np.array([nb, nblk], dtype=np.uint32).tobytes()
+        stream = np.frombuffer(hdr + off.tobytes() + b"".join(pays), dtype=np.uint8)
+        got = host(bsg.decompress_sync(dev(stream), nblk * nb, E, nb))
+        assert np.array_equal(got, expect)
+
+
 def test_decode_rejects_corruption(bsg):
     E, nb = 4, 2048
     x = synth.gen_gauss_int32(2048 * 8 + 5, 6, 2)
