@@ -568,19 +568,27 @@ __device__ __forceinline__ void put_word(uint32_t *b32, int w, uint32_t v, uint3
 // out[op, op + len) = buf[src, src + len) for src >= op (literals: every step
 // reads before it writes, and a later step never reads a dword an earlier
 // step wrote) or src + len <= op (a match without overlap).
+__device__ __forceinline__ void dcopy_step(uint32_t *b32, int w, int w1, int delta, uint32_t sh,
+                                           int op, int end)
+{
+    if (w < w1) {
+        const int a = (4 * w + delta) >> 2;
+        const uint32_t old = b32[w];
+        put_word(b32, w, __builtin_amdgcn_alignbyte(b32[a + 1], b32[a], sh), old, op, end);
+    }
+}
+
+// (the first step is peeled: most runs fit one step of the wave, and the
+// loop's per-lane induction updates would be wasted on it)
 __device__ __forceinline__ void dcopy(uint32_t *b32, int op, int src, int len)
 {
     const int w0 = op >> 2, w1 = (op + len + 3) >> 2, end = op + len;
+    if (w0 >= w1) return;
     const int delta = src - op;
     const uint32_t sh = (uint32_t)(delta & 3);
-    for (int b = w0; b < w1; b += kWave) {
-        const int w = b + (int)threadIdx.x;
-        if (w < w1) {
-            const int a = (4 * w + delta) >> 2;
-            const uint32_t old = b32[w];
-            put_word(b32, w, __builtin_amdgcn_alignbyte(b32[a + 1], b32[a], sh), old, op, end);
-        }
-    }
+    dcopy_step(b32, w0 + (int)threadIdx.x, w1, delta, sh, op, end);
+    for (int b = w0 + kWave; b < w1; b += kWave)
+        dcopy_step(b32, b + (int)threadIdx.x, w1, delta, sh, op, end);
 }
 
 // LZ4 match: out[op + i] = out[op - off + (i mod off)] for i < len.  Every
