@@ -582,8 +582,8 @@ __device__ __forceinline__ void dcopy_step(uint32_t *b32, int w, int w1, int del
 // loop's per-lane induction updates would be wasted on it)
 __device__ __forceinline__ void dcopy(uint32_t *b32, int op, int src, int len)
 {
+    if (len <= 0) return; // (a sequence without literals: a quarter of them)
     const int w0 = op >> 2, w1 = (op + len + 3) >> 2, end = op + len;
-    if (w0 >= w1) return;
     const int delta = src - op;
     const uint32_t sh = (uint32_t)(delta & 3);
     dcopy_step(b32, w0 + (int)threadIdx.x, w1, delta, sh, op, end);
@@ -609,55 +609,60 @@ __device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
     // inside that), floor(x M / 2^32) = floor(x / off) for 0 <= x <= 256.
     // The lane's byte offset x = 4 (w0 + lane) - op lies in [-3, 252]; a
     // negative one (lane 0) is below off, so one or two periods lift it.
-    // (For off = 1 the value is not used.)
-    const uint32_t M = (uint32_t)__builtin_amdgcn_readfirstlane(
-                           (int)(uint32_t)(__builtin_amdgcn_rcpf((float)off) * 4294971392.0f)) + 1u;
+    // (For off = 1 the values are not used, and 2^32 / off does not fit.)
+    const float mf = __builtin_amdgcn_rcpf((float)off) * 4294971392.0f;
+    const uint32_t M =
+        off > 1 ? (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)mf) + 1u : 0u;
     const int x = 4 * (w0 + (int)threadIdx.x) - op;
     int r = x >= 0 ? x - off * (int)__umulhi((uint32_t)x, M) : (x + off >= 0 ? x + off : x + 2 * off);
     const int step = 4 * kWave - off * (int)__umulhi(4u * kWave, M);
+    // the wave's steps over [w0, w1), the first one peeled (most matches fit
+    // one step); r advances by step mod off between steps
+    const auto steps = [&](auto body) {
+        body(w0 + (int)threadIdx.x, r);
+        for (int b = w0 + kWave; b < w1; b += kWave) {
+            r += step;
+            if (r >= off) r -= off;
+            body(b + (int)threadIdx.x, r);
+        }
+    };
     if (off < 4) { // a period of 1..3 bytes, replicated from registers
         const uint32_t p0 = b8[base], p1 = b8[base + (off > 1 ? 1 : 0)],
                        p2 = b8[base + (off > 2 ? 2 : 0)];
-        for (int b = w0; b < w1; b += kWave) {
-            const int w = b + (int)threadIdx.x;
+        steps([&](int w, int rr) {
             if (w < w1) {
                 const uint32_t old = b32[w];
                 uint32_t v;
                 if (off == 1) {
                     v = p0 * 0x01010101u;
                 } else if (off == 2) {
-                    v = (r == 0 ? (p0 | (p1 << 8)) : (p1 | (p0 << 8))) * 0x00010001u;
+                    v = (rr == 0 ? (p0 | (p1 << 8)) : (p1 | (p0 << 8))) * 0x00010001u;
                 } else {
-                    const uint32_t a = r == 0 ? p0 : (r == 1 ? p1 : p2);
-                    const uint32_t c1 = r == 0 ? p1 : (r == 1 ? p2 : p0);
-                    const uint32_t c2 = r == 0 ? p2 : (r == 1 ? p0 : p1);
+                    const uint32_t a = rr == 0 ? p0 : (rr == 1 ? p1 : p2);
+                    const uint32_t c1 = rr == 0 ? p1 : (rr == 1 ? p2 : p0);
+                    const uint32_t c2 = rr == 0 ? p2 : (rr == 1 ? p0 : p1);
                     v = a | (c1 << 8) | (c2 << 16) | (a << 24);
                 }
                 put_word(b32, w, v, old, op, end);
             }
-            r += step;
-            if (r >= off) r -= off;
-        }
+        });
         return;
     }
     const uint32_t head = __builtin_amdgcn_alignbyte(b32[(base >> 2) + 1], b32[base >> 2],
                                                      (uint32_t)(base & 3));
-    for (int b = w0; b < w1; b += kWave) {
-        const int w = b + (int)threadIdx.x;
+    steps([&](int w, int rr) {
         if (w < w1) {
             const uint32_t old = b32[w];
-            // 4 bytes of the period from r; where they run past its end
-            // (k = off - r < 4 of them), the rest comes from its start
-            const int sidx = base + r;
+            // 4 bytes of the period from rr; where they run past its end
+            // (k = off - rr < 4 of them), the rest comes from its start
+            const int sidx = base + rr;
             uint32_t v = __builtin_amdgcn_alignbyte(b32[(sidx >> 2) + 1], b32[sidx >> 2],
                                                     (uint32_t)(sidx & 3));
-            const int k = off - r;
+            const int k = off - rr;
             if (k < 4) v = (v & ((1u << (8 * k)) - 1u)) | (head << (8 * k));
             put_word(b32, w, v, old, op, end);
         }
-        r += step;
-        if (r >= off) r -= off;
-    }
+    });
 }
 
 // Decode the LZ4 block held at buf[ip0, iend) into buf[0, ob) in place (the
