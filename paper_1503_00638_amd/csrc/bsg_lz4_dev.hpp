@@ -591,6 +591,47 @@ __device__ __forceinline__ void dcopy(uint32_t *b32, int op, int src, int len)
         dcopy_step(b32, b + (int)threadIdx.x, w1, delta, sh, op, end);
 }
 
+// One wave step of an overlapping match, for dword w (r: the byte offset of
+// the dword's first byte from op, mod off).  Period 1..3: the dword is built
+// from the period's bytes p0..p2.
+__device__ __forceinline__ void dmatch_step_short(uint32_t *b32, int w, int w1, int r, int off,
+                                                  uint32_t p0, uint32_t p1, uint32_t p2, int op,
+                                                  int end)
+{
+    if (w < w1) {
+        const uint32_t old = b32[w];
+        uint32_t v;
+        if (off == 1) {
+            v = p0 * 0x01010101u;
+        } else if (off == 2) {
+            v = (r == 0 ? (p0 | (p1 << 8)) : (p1 | (p0 << 8))) * 0x00010001u;
+        } else {
+            const uint32_t a = r == 0 ? p0 : (r == 1 ? p1 : p2);
+            const uint32_t c1 = r == 0 ? p1 : (r == 1 ? p2 : p0);
+            const uint32_t c2 = r == 0 ? p2 : (r == 1 ? p0 : p1);
+            v = a | (c1 << 8) | (c2 << 16) | (a << 24);
+        }
+        put_word(b32, w, v, old, op, end);
+    }
+}
+
+// Period of 4 bytes or more starting at base: 4 bytes of it from r; where
+// they run past its end (k = off - r < 4 of them), the rest comes from its
+// start (head: its first dword).
+__device__ __forceinline__ void dmatch_step(uint32_t *b32, int w, int w1, int r, int off, int base,
+                                            uint32_t head, int op, int end)
+{
+    if (w < w1) {
+        const uint32_t old = b32[w];
+        const int sidx = base + r;
+        uint32_t v = __builtin_amdgcn_alignbyte(b32[(sidx >> 2) + 1], b32[sidx >> 2],
+                                                (uint32_t)(sidx & 3));
+        const int k = off - r;
+        if (k < 4) v = (v & ((1u << (8 * k)) - 1u)) | (head << (8 * k));
+        put_word(b32, w, v, old, op, end);
+    }
+}
+
 // LZ4 match: out[op + i] = out[op - off + (i mod off)] for i < len.  Every
 // source byte lies in [op - off, op), final before the match starts, so all
 // steps are independent.  Lane state r = (byte offset of its dword from op)
@@ -616,53 +657,26 @@ __device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
     const int x = 4 * (w0 + (int)threadIdx.x) - op;
     int r = x >= 0 ? x - off * (int)__umulhi((uint32_t)x, M) : (x + off >= 0 ? x + off : x + 2 * off);
     const int step = 4 * kWave - off * (int)__umulhi(4u * kWave, M);
-    // the wave's steps over [w0, w1), the first one peeled (most matches fit
-    // one step); r advances by step mod off between steps
-    const auto steps = [&](auto body) {
-        body(w0 + (int)threadIdx.x, r);
-        for (int b = w0 + kWave; b < w1; b += kWave) {
-            r += step;
-            if (r >= off) r -= off;
-            body(b + (int)threadIdx.x, r);
-        }
-    };
     if (off < 4) { // a period of 1..3 bytes, replicated from registers
         const uint32_t p0 = b8[base], p1 = b8[base + (off > 1 ? 1 : 0)],
                        p2 = b8[base + (off > 2 ? 2 : 0)];
-        steps([&](int w, int rr) {
-            if (w < w1) {
-                const uint32_t old = b32[w];
-                uint32_t v;
-                if (off == 1) {
-                    v = p0 * 0x01010101u;
-                } else if (off == 2) {
-                    v = (rr == 0 ? (p0 | (p1 << 8)) : (p1 | (p0 << 8))) * 0x00010001u;
-                } else {
-                    const uint32_t a = rr == 0 ? p0 : (rr == 1 ? p1 : p2);
-                    const uint32_t c1 = rr == 0 ? p1 : (rr == 1 ? p2 : p0);
-                    const uint32_t c2 = rr == 0 ? p2 : (rr == 1 ? p0 : p1);
-                    v = a | (c1 << 8) | (c2 << 16) | (a << 24);
-                }
-                put_word(b32, w, v, old, op, end);
-            }
-        });
+        // the first step peeled (most matches fit one step of the wave)
+        dmatch_step_short(b32, w0 + (int)threadIdx.x, w1, r, off, p0, p1, p2, op, end);
+        for (int b = w0 + kWave; b < w1; b += kWave) {
+            r += step;
+            if (r >= off) r -= off;
+            dmatch_step_short(b32, b + (int)threadIdx.x, w1, r, off, p0, p1, p2, op, end);
+        }
         return;
     }
     const uint32_t head = __builtin_amdgcn_alignbyte(b32[(base >> 2) + 1], b32[base >> 2],
                                                      (uint32_t)(base & 3));
-    steps([&](int w, int rr) {
-        if (w < w1) {
-            const uint32_t old = b32[w];
-            // 4 bytes of the period from rr; where they run past its end
-            // (k = off - rr < 4 of them), the rest comes from its start
-            const int sidx = base + rr;
-            uint32_t v = __builtin_amdgcn_alignbyte(b32[(sidx >> 2) + 1], b32[sidx >> 2],
-                                                    (uint32_t)(sidx & 3));
-            const int k = off - rr;
-            if (k < 4) v = (v & ((1u << (8 * k)) - 1u)) | (head << (8 * k));
-            put_word(b32, w, v, old, op, end);
-        }
-    });
+    dmatch_step(b32, w0 + (int)threadIdx.x, w1, r, off, base, head, op, end);
+    for (int b = w0 + kWave; b < w1; b += kWave) {
+        r += step;
+        if (r >= off) r -= off;
+        dmatch_step(b32, b + (int)threadIdx.x, w1, r, off, base, head, op, end);
+    }
 }
 
 // Decode the LZ4 block held at buf[ip0, iend) into buf[0, ob) in place (the

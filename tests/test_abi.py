@@ -95,3 +95,44 @@ def test_batch_table_host_calls(L):
     assert L.bsg_batch_build_table(big, 1, buf, t3) == -1
     assert L.bsg_batch_compress(buf, None, vp(256), vp(256), 1 << 20, 0, None) == -1
     assert L.bsg_batch_decompress(buf, vp(17), vp(256), 0, None) == -1
+
+
+def _gfx950_kernel_metadata(lib_path, tmp_path):
+    """(kernel name, private segment bytes per lane) of every kernel in the
+    library's gfx950 code objects (one offload bundle per source file)."""
+    import shutil
+    import subprocess
+    llvm = "/opt/rocm/llvm/bin"
+    tools = [shutil.which("objcopy"), os.path.join(llvm, "clang-offload-bundler"),
+             os.path.join(llvm, "llvm-readelf")]
+    if tools[0] is None or not all(os.path.exists(t) for t in tools[1:]):
+        pytest.skip("no objcopy / clang-offload-bundler / llvm-readelf")
+    fat = tmp_path / "fatbin.bin"
+    subprocess.run([tools[0], "--dump-section", f".hip_fatbin={fat}", lib_path], check=True)
+    data = fat.read_bytes()
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    starts = [m.start() for m in re.finditer(re.escape(magic), data)] + [len(data)]
+    out = []
+    for k in range(len(starts) - 1):
+        b = tmp_path / f"b{k}.bin"
+        co = tmp_path / f"c{k}.co"
+        b.write_bytes(data[starts[k]:starts[k + 1]])
+        subprocess.run([tools[1], "--unbundle", "--type=o", f"--input={b}",
+                        "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--output={co}"], check=True)
+        notes = subprocess.run([tools[2], "--notes", str(co)], capture_output=True, text=True,
+                               check=True).stdout.splitlines()
+        names = [l.split(":", 1)[1].strip() for l in notes if l.strip().startswith(".name:")]
+        sizes = [int(l.split(":", 1)[1]) for l in notes if "private_segment_fixed_size" in l]
+        assert len(names) == len(sizes)
+        out += list(zip(names, sizes))
+    return out
+
+
+def test_kernels_use_no_scratch(L, tmp_path):
+    """No kernel spills to scratch (per-lane private memory in HBM): every
+    kernel's private segment is empty."""
+    from paper_1503_00638_amd import _lib
+    meta = _gfx950_kernel_metadata(_lib.LIB_PATH, tmp_path)
+    assert any("k_encode" in n for n, _ in meta) and any("k_decode" in n for n, _ in meta)
+    spill = [(n, s) for n, s in meta if s != 0]
+    assert not spill, spill
