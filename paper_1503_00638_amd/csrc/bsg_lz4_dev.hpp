@@ -546,12 +546,16 @@ __device__ __forceinline__ bool read_len_ext(const uint8_t *ci, int &ip, int ien
 // and each lane builds one dword per step from its source bytes and writes it
 // with one aligned store.  Bytes of the first and last dword outside the
 // range keep their old value (final output below, or input not yet read
-// above: rewritten unchanged).  Sources may lie up to 3 bytes before b32[0],
-// so the buffer has a padding dword in front.
+// above: rewritten unchanged).  Every lane of a step takes part, no exec
+// mask: a lane past the range (up to 63 dwords past it) reads its dword and
+// sources and writes the dword back unchanged, so the buffer has 64 dwords
+// of padding after it.  Sources may lie up to 3 bytes before b32[0], so the
+// buffer has a padding dword in front.
 __device__ __forceinline__ uint32_t range_mask(int d, int op, int end)
 {
     const int lo = op - d > 0 ? op - d : 0; // 0..3
-    const int hi = end - d < 4 ? end - d : 4; // 1..4
+    const int e = end - d;
+    const int hi = e < 4 ? (e > 0 ? e : 0) : 4; // 0..4 (0: past the range)
     const uint32_t mhi = hi >= 4 ? 0xFFFFFFFFu : ((1u << (8 * hi)) - 1u);
     return mhi & ~((1u << (8 * lo)) - 1u);
 }
@@ -568,14 +572,12 @@ __device__ __forceinline__ void put_word(uint32_t *b32, int w, uint32_t v, uint3
 // out[op, op + len) = buf[src, src + len) for src >= op (literals: every step
 // reads before it writes, and a later step never reads a dword an earlier
 // step wrote) or src + len <= op (a match without overlap).
-__device__ __forceinline__ void dcopy_step(uint32_t *b32, int w, int w1, int delta, uint32_t sh,
-                                           int op, int end)
+__device__ __forceinline__ void dcopy_step(uint32_t *b32, int w, int delta, uint32_t sh, int op,
+                                           int end)
 {
-    if (w < w1) {
-        const int a = (4 * w + delta) >> 2;
-        const uint32_t old = b32[w];
-        put_word(b32, w, __builtin_amdgcn_alignbyte(b32[a + 1], b32[a], sh), old, op, end);
-    }
+    const int a = (4 * w + delta) >> 2;
+    const uint32_t old = b32[w];
+    put_word(b32, w, __builtin_amdgcn_alignbyte(b32[a + 1], b32[a], sh), old, op, end);
 }
 
 // (the first step is peeled: most runs fit one step of the wave, and the
@@ -586,50 +588,45 @@ __device__ __forceinline__ void dcopy(uint32_t *b32, int op, int src, int len)
     const int w0 = op >> 2, w1 = (op + len + 3) >> 2, end = op + len;
     const int delta = src - op;
     const uint32_t sh = (uint32_t)(delta & 3);
-    dcopy_step(b32, w0 + (int)threadIdx.x, w1, delta, sh, op, end);
+    dcopy_step(b32, w0 + (int)threadIdx.x, delta, sh, op, end);
     for (int b = w0 + kWave; b < w1; b += kWave)
-        dcopy_step(b32, b + (int)threadIdx.x, w1, delta, sh, op, end);
+        dcopy_step(b32, b + (int)threadIdx.x, delta, sh, op, end);
 }
 
 // One wave step of an overlapping match, for dword w (r: the byte offset of
 // the dword's first byte from op, mod off).  Period 1..3: the dword is built
 // from the period's bytes p0..p2.
-__device__ __forceinline__ void dmatch_step_short(uint32_t *b32, int w, int w1, int r, int off,
-                                                  uint32_t p0, uint32_t p1, uint32_t p2, int op,
-                                                  int end)
+__device__ __forceinline__ void dmatch_step_short(uint32_t *b32, int w, int r, int off, uint32_t p0,
+                                                  uint32_t p1, uint32_t p2, int op, int end)
 {
-    if (w < w1) {
-        const uint32_t old = b32[w];
-        uint32_t v;
-        if (off == 1) {
-            v = p0 * 0x01010101u;
-        } else if (off == 2) {
-            v = (r == 0 ? (p0 | (p1 << 8)) : (p1 | (p0 << 8))) * 0x00010001u;
-        } else {
-            const uint32_t a = r == 0 ? p0 : (r == 1 ? p1 : p2);
-            const uint32_t c1 = r == 0 ? p1 : (r == 1 ? p2 : p0);
-            const uint32_t c2 = r == 0 ? p2 : (r == 1 ? p0 : p1);
-            v = a | (c1 << 8) | (c2 << 16) | (a << 24);
-        }
-        put_word(b32, w, v, old, op, end);
+    const uint32_t old = b32[w];
+    uint32_t v;
+    if (off == 1) {
+        v = p0 * 0x01010101u;
+    } else if (off == 2) {
+        v = (r == 0 ? (p0 | (p1 << 8)) : (p1 | (p0 << 8))) * 0x00010001u;
+    } else {
+        const uint32_t a = r == 0 ? p0 : (r == 1 ? p1 : p2);
+        const uint32_t c1 = r == 0 ? p1 : (r == 1 ? p2 : p0);
+        const uint32_t c2 = r == 0 ? p2 : (r == 1 ? p0 : p1);
+        v = a | (c1 << 8) | (c2 << 16) | (a << 24);
     }
+    put_word(b32, w, v, old, op, end);
 }
 
 // Period of 4 bytes or more starting at base: 4 bytes of it from r; where
 // they run past its end (k = off - r < 4 of them), the rest comes from its
 // start (head: its first dword).
-__device__ __forceinline__ void dmatch_step(uint32_t *b32, int w, int w1, int r, int off, int base,
+__device__ __forceinline__ void dmatch_step(uint32_t *b32, int w, int r, int off, int base,
                                             uint32_t head, int op, int end)
 {
-    if (w < w1) {
-        const uint32_t old = b32[w];
-        const int sidx = base + r;
-        uint32_t v = __builtin_amdgcn_alignbyte(b32[(sidx >> 2) + 1], b32[sidx >> 2],
-                                                (uint32_t)(sidx & 3));
-        const int k = off - r;
-        if (k < 4) v = (v & ((1u << (8 * k)) - 1u)) | (head << (8 * k));
-        put_word(b32, w, v, old, op, end);
-    }
+    const uint32_t old = b32[w];
+    const int sidx = base + r;
+    uint32_t v = __builtin_amdgcn_alignbyte(b32[(sidx >> 2) + 1], b32[sidx >> 2],
+                                            (uint32_t)(sidx & 3));
+    const int k = off - r;
+    if (k < 4) v = (v & ((1u << (8 * k)) - 1u)) | (head << (8 * k));
+    put_word(b32, w, v, old, op, end);
 }
 
 // LZ4 match: out[op + i] = out[op - off + (i mod off)] for i < len.  Every
@@ -661,21 +658,21 @@ __device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
         const uint32_t p0 = b8[base], p1 = b8[base + (off > 1 ? 1 : 0)],
                        p2 = b8[base + (off > 2 ? 2 : 0)];
         // the first step peeled (most matches fit one step of the wave)
-        dmatch_step_short(b32, w0 + (int)threadIdx.x, w1, r, off, p0, p1, p2, op, end);
+        dmatch_step_short(b32, w0 + (int)threadIdx.x, r, off, p0, p1, p2, op, end);
         for (int b = w0 + kWave; b < w1; b += kWave) {
             r += step;
             if (r >= off) r -= off;
-            dmatch_step_short(b32, b + (int)threadIdx.x, w1, r, off, p0, p1, p2, op, end);
+            dmatch_step_short(b32, b + (int)threadIdx.x, r, off, p0, p1, p2, op, end);
         }
         return;
     }
     const uint32_t head = __builtin_amdgcn_alignbyte(b32[(base >> 2) + 1], b32[base >> 2],
                                                      (uint32_t)(base & 3));
-    dmatch_step(b32, w0 + (int)threadIdx.x, w1, r, off, base, head, op, end);
+    dmatch_step(b32, w0 + (int)threadIdx.x, r, off, base, head, op, end);
     for (int b = w0 + kWave; b < w1; b += kWave) {
         r += step;
         if (r >= off) r -= off;
-        dmatch_step(b32, b + (int)threadIdx.x, w1, r, off, base, head, op, end);
+        dmatch_step(b32, b + (int)threadIdx.x, r, off, base, head, op, end);
     }
 }
 
@@ -871,7 +868,9 @@ __device__ __forceinline__ int encode_one(const uint8_t *__restrict__ src, int64
 }
 
 template <int MAXB> struct DecLds {
-    uint32_t buf32[dec_buf_bytes<MAXB>() / 4 + 8]; // + a padding dword in front, over-read after
+    // + 4 dwords in front (one readable padding dword before the buffer),
+    // 4 over-read after, and 64 for the copy lanes past a range
+    uint32_t buf32[dec_buf_bytes<MAXB>() / 4 + 8 + kWave];
 };
 
 // Decode block b of a stream (payload / off as laid out in the stream) into
