@@ -389,6 +389,55 @@ def test_decode_rejects_corruption(bsg):
     assert n_err > 20
 
 
+def _lz4_len(n):
+    """LZ4 length continuation bytes for a length field value n >= 15."""
+    out, r = [], n - 15
+    while r >= 255:
+        out.append(255)
+        r -= 255
+    return out + [r]
+
+
+def test_decode_rejects_overlong_literals(bsg):
+    """Blocks whose literal runs end past the block (as the last sequence,
+    or before a match) and a block with no bytes at all are rejected, as by
+    the oracle, and the blocks around them still decode."""
+    E, nb = 4, 2048
+    n = nb * E
+    rng = np.random.default_rng(23)
+    lit = rng.integers(0, 256, n + 64, dtype=np.uint8).tobytes()
+    good = oracle.lz4_compress_block(np.frombuffer(lit[:n], np.uint8))
+
+    def seq(ll, body, off=None, ml=None):
+        tok = (min(ll, 15) << 4) | (0 if ml is None else min(ml - 4, 15))
+        b = bytes([tok] + (_lz4_len(ll) if ll >= 15 else [])) + body[:ll]
+        if ml is not None:
+            b += bytes([off & 255, off >> 8]) + bytes(_lz4_len(ml - 4) if ml - 4 >= 15 else [])
+        return b
+
+    bad_blocks = [
+        seq(n + 5, lit),                                  # last literals past the block
+        seq(n - 2, lit, off=1, ml=10) + seq(0, b""),      # match past the block
+        seq(n + 3, lit, off=1, ml=4) + seq(0, b""),       # literals past it, then a match
+        b"",                                              # no token at all
+    ]
+    for bad in bad_blocks:
+        with pytest.raises(oracle.OracleError):
+            oracle.lz4_decompress_block(bad, n)
+        pays = [good, bad, good]
+        off = np.zeros(4, dtype=np.uint64)
+        off[1:] = np.cumsum([len(q) for q in pays])
+        hdr = np.array([0x31475342, E], dtype=np.uint32).tobytes() + \
+            np.array([3 * nb], dtype=np.uint64).tobytes() + \
+            np.array([nb, 3], dtype=np.uint32).tobytes()
+        stream = np.frombuffer(hdr + off.tobytes() + b"".join(pays), dtype=np.uint8)
+        out, st = bsg.decompress(dev(stream), stream.size, 3 * nb, E, nb)
+        assert int(host(st)[0]) == -3, len(bad)
+        got = host(out)
+        expect = oracle.bitunshuffle(np.frombuffer(lit[:n], np.uint8), E, nb)
+        assert np.array_equal(got[:n], expect) and np.array_equal(got[2 * n:3 * n], expect)
+
+
 def test_capacity_verdict(bsg):
     x = np.random.default_rng(0).integers(0, 256, 2048 * 4 * 4, dtype=np.uint8)
     ref = oracle.compress(x, 4, 2048)
