@@ -380,8 +380,7 @@ __device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table,
         const uint32_t *d = FULL ? dg + cc * (kChunk / 4) : b32 + (pc >> 2);
         vv[cc] = __builtin_amdgcn_alignbyte(d[1], d[0], (uint32_t)(pc & 3));
     }
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc) {
+    const auto chunk = [&](int cc) {
         // (chunks past last_q only insert positions that no lookup sees)
         const int c0 = g0 + cc * kChunk;
         const int p = c0 + lane;
@@ -398,7 +397,30 @@ __device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table,
         const bool run_on = lane != kWave - 1 && (FULL || p + 1 <= last_ins) && vn == v;
         if ((FULL || p <= last_ins) && !run_on)
             atomicMax(&table[h], (uint32_t)(p + 1));
+    };
+    chunk(0);
+    if constexpr (FULL) {
+        // A group holding one 4-byte value at every position (half of the
+        // groups of a rounded visibility block: its constant bit planes).
+        // Chunk 0 went the usual way and left the entry at its last
+        // position; chunk k > 0 would find the last position of chunk k - 1
+        // and the entry would end at the group's last position, so the rest
+        // takes one write instead of 7 reads and 7 inserts.  (The test runs
+        // while chunk 0's table accesses are in flight.)
+        const uint32_t v0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)vv[0]);
+        uint32_t x = 0;
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) x |= vv[cc] ^ v0;
+        if (__ballot(x != 0) == 0) {
+#pragma unroll
+            for (int cc = 1; cc < NC; ++cc) candv[cc] = (uint32_t)(g0 + cc * kChunk);
+            if (lane == kWave - 1)
+                table[(v0 * kHashMult) >> (32 - kHashBits)] = (uint32_t)(g0 + kGroup);
+            return;
+        }
     }
+#pragma unroll
+    for (int cc = 1; cc < NC; ++cc) chunk(cc);
 }
 
 // The mask of the chunk's positions (from c0, a multiple of 64) whose

@@ -389,6 +389,36 @@ def test_decode_rejects_corruption(bsg):
     assert n_err > 20
 
 
+def test_compress_near_uniform_groups(bsg):
+    """Blocks whose LZ4 input (the transposed block) is one byte value except
+    for a single byte at the edges of a 512-position hash group (the group's
+    last window reaches 3 bytes into the next one), and blocks whose value
+    changes exactly at group boundaries: the stream equals the oracle's and
+    decodes back."""
+    E, nb = 4, 2048
+    n = nb * E
+    blocks = []
+    for g0 in (0, 1536, 7168):
+        for k in (0, 1, 63, 64, 65, 511, 512, 513, 514, 515):
+            if g0 + k < n:
+                t = np.full(n, 0x33, dtype=np.uint8)
+                t[g0 + k] = 0x5A
+                blocks.append(t)
+    t = np.repeat(np.arange(16, dtype=np.uint8) * 17, 512)
+    blocks.append(t)
+    t = t.copy()
+    t[512 * 3 - 1] = 0
+    blocks.append(t)
+    blocks.append(np.zeros(n, dtype=np.uint8))
+    trans = np.concatenate(blocks)
+    data = oracle.bitunshuffle(trans, E, nb)
+    ref = oracle.compress(data, E, nb)
+    got = host(bsg.compress_sync(dev(data), E, nb))
+    assert np.array_equal(got, ref)
+    back = host(bsg.decompress_sync(dev(ref), data.size // E, E, nb))
+    assert np.array_equal(back, data)
+
+
 def _lz4_len(n):
     """LZ4 length continuation bytes for a length field value n >= 15."""
     out, r = [], n - 15
