@@ -107,8 +107,13 @@ def _gfx950_kernel_metadata(lib_path, tmp_path):
              os.path.join(llvm, "llvm-readelf")]
     if tools[0] is None or not all(os.path.exists(t) for t in tools[1:]):
         pytest.skip("no objcopy / clang-offload-bundler / llvm-readelf")
+    # objcopy rewrites the file it reads unless given an output file: work on
+    # a copy, so the library this process has loaded is never touched
+    lib_copy = tmp_path / "lib.so"
+    shutil.copyfile(lib_path, lib_copy)
     fat = tmp_path / "fatbin.bin"
-    subprocess.run([tools[0], "--dump-section", f".hip_fatbin={fat}", lib_path], check=True)
+    subprocess.run([tools[0], "--dump-section", f".hip_fatbin={fat}", str(lib_copy),
+                    str(tmp_path / "lib_out.so")], check=True)
     data = fat.read_bytes()
     magic = b"__CLANG_OFFLOAD_BUNDLE__"
     starts = [m.start() for m in re.finditer(re.escape(magic), data)] + [len(data)]
