@@ -56,25 +56,55 @@ def traffic_for(kernel: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def host_description():
+    """CPU model and core counts of the machine the oracle baseline runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(vis, autos, w, n_freq):
+    """The oracle on the host's cores over the first n_freq frequencies:
+    round + compress, then decompress, with the OpenMP thread count the
+    process allows (blocks spread over threads) and with one thread (the
+    setting of the paper's single-core figures)."""
     import oracle
     oracle.build(force=False)
     threads = oracle.max_threads()
     v = np.ascontiguousarray(vis[:n_freq])
     a = np.ascontiguousarray(autos[:n_freq])
     nb = w["block_bytes"] // 4
-    t0 = time.perf_counter()
-    r = oracle.round_to_noise(v, a, w["N"], w["f"], nthreads=threads)
-    s = oracle.compress(r, 4, nb, nthreads=threads)
-    t1 = time.perf_counter()
-    d = oracle.decompress(s, r.size * 2, 4, nb, nthreads=threads)
-    t2 = time.perf_counter()
-    assert np.array_equal(d, r.view(np.uint8).reshape(-1))
     U = v.nbytes
-    return {"value": U / (t2 - t0) / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_freq} of {vis.shape[0]} frequencies ({U / 1e9:.3f} GB): "
-                      f"round+compress {U / (t1 - t0) / 1e9:.3f} GB/s, decompress "
-                      f"{U / (t2 - t1) / 1e9:.3f} GB/s, ratio {s.size / U:.4f}"}
+
+    def run(nthreads):
+        t0 = time.perf_counter()
+        r = oracle.round_to_noise(v, a, w["N"], w["f"], nthreads=nthreads)
+        s = oracle.compress(r, 4, nb, nthreads=nthreads)
+        t1 = time.perf_counter()
+        d = oracle.decompress(s, r.size * 2, 4, nb, nthreads=nthreads)
+        t2 = time.perf_counter()
+        assert np.array_equal(d, r.view(np.uint8).reshape(-1))
+        return {"value": round(U / (t2 - t0) / 1e9, 4),
+                "round_compress_GBps": round(U / (t1 - t0) / 1e9, 4),
+                "decompress_GBps": round(U / (t2 - t1) / 1e9, 4), "ratio": round(s.size / U, 5)}
+
+    multi = run(threads)
+    single = run(1)
+    return {"value": multi["value"], "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_freq} of {vis.shape[0]} frequencies ({U / 1e9:.3f} GB), "
+                      f"round+compress then decompress: {threads} threads "
+                      f"{multi['round_compress_GBps']:.3f} / {multi['decompress_GBps']:.3f} GB/s, "
+                      f"1 thread {single['round_compress_GBps']:.3f} / "
+                      f"{single['decompress_GBps']:.3f} GB/s, ratio {multi['ratio']:.4f}",
+            "threads": multi, "single_thread": single, "host": host_description()}
 
 
 def main(argv=None):
@@ -82,7 +112,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-freqs", type=int, default=256,
+    ap.add_argument("--cpu-freqs", type=int, default=128,
                     help="frequencies of the workload the CPU oracle baseline times")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",

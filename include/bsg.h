@@ -92,7 +92,10 @@ int64_t bsg_block_elems(int64_t elem_size, int64_t block_size);
  *   of zero is kept.
  * Errors: BSG_EINVAL for negative sizes, NULL pointers with a non-empty
  *   array, n_samples <= 0 or f < 0 or non-finite; BSG_EHIP on launch failure.
- *   Entries of prod_map outside [0, I) are not checked on the device. */
+ *   Entries of prod_map outside [0, I) are not checked here (that would
+ *   need a device read); the kernels index autos with them, so such a map
+ *   reads out of bounds and can fault.  The caller validates the map (the
+ *   Python binding does, before every call that takes one). */
 int bsg_round_to_noise(const void *vis_in, void *vis_out, const float *autos, int64_t F,
                        int64_t I, int64_t T, const int32_t *prod_map, double n_samples,
                        double f, void *stream);

@@ -54,6 +54,32 @@ def _nbytes(t: torch.Tensor) -> int:
     return t.numel() * t.element_size()
 
 
+def _check_out(out: torch.Tensor, nbytes: int, what: str) -> None:
+    """A caller-supplied output must hold the bytes the call writes (the C-ABI
+    takes raw pointers and cannot check)."""
+    if _nbytes(out) < nbytes:
+        raise ValueError(f"{what}: output holds {_nbytes(out)} bytes, the call writes {nbytes}")
+
+
+def _check_word(t: torch.Tensor, dtype, what: str) -> None:
+    """Device result words (stream length, decode status) the kernels write."""
+    if t.dtype != dtype or t.numel() < 1:
+        raise ValueError(f"{what} must be a {dtype} tensor of at least one element")
+
+
+def _check_prod_map(prod_map: torch.Tensor | None, P: int, I: int) -> None:
+    """prod_map must be int32 (P, 2) with every entry in [0, I): the kernels
+    index the autos with it and do not check it."""
+    if prod_map is None:
+        return
+    if prod_map.dtype != torch.int32 or tuple(prod_map.shape) != (P, 2):
+        raise ValueError("prod_map must be int32 (P, 2)")
+    if prod_map.numel():
+        lo, hi = torch.aminmax(prod_map)
+        if int(lo.item()) < 0 or int(hi.item()) >= I:
+            raise ValueError(f"prod_map entries must lie in [0, {I})")
+
+
 def block_elems(elem_size: int, block_size: int = 0) -> int:
     r = _lib.lib().bsg_block_elems(elem_size, block_size)
     if r < 0:
@@ -74,8 +100,8 @@ def round_to_noise(vis: torch.Tensor, autos: torch.Tensor, n_samples: float, f: 
         raise ValueError(f"vis {tuple(vis.shape)} does not match autos {tuple(autos.shape)}")
     if out is None:
         out = torch.empty_like(vis)
-    if prod_map is not None and (prod_map.dtype != torch.int32 or tuple(prod_map.shape) != (vis.shape[1], 2)):
-        raise ValueError("prod_map must be int32 (P, 2)")
+    _check_out(out, _nbytes(vis), "vis_out")
+    _check_prod_map(prod_map, vis.shape[1], I)
     _lib.check(_lib.lib().bsg_round_to_noise(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
                                               _ptr(prod_map), float(n_samples), float(f),
                                               _stream_ptr(stream)), "round_to_noise")
@@ -97,8 +123,10 @@ def noise_compensation(vis: torch.Tensor, autos: torch.Tensor, prod_map: torch.T
     the diagonal noise model (Section 3.2)."""
     _require_device(vis, autos, prod_map, out)
     F, I, T = _vis_autos(vis, autos)
+    _check_prod_map(prod_map, vis.shape[1], I)
     if out is None:
         out = torch.empty((F, T), dtype=torch.float64, device=vis.device)
+    _check_out(out, 8 * F * T, "scale")
     _lib.check(_lib.lib().bsg_noise_compensation(_ptr(vis), _ptr(autos), F, I, T, _ptr(prod_map),
                                                   _ptr(out), _stream_ptr(stream)),
                "noise_compensation")
@@ -113,8 +141,10 @@ def round_to_noise_scaled(vis: torch.Tensor, autos: torch.Tensor, n_samples: flo
     F, I, T = _vis_autos(vis, autos)
     if scale.dtype != torch.float64 or tuple(scale.shape) != (F, T):
         raise ValueError("scale must be float64 (F, T)")
+    _check_prod_map(prod_map, vis.shape[1], I)
     if out is None:
         out = torch.empty_like(vis)
+    _check_out(out, _nbytes(vis), "vis_out")
     _lib.check(_lib.lib().bsg_round_to_noise_scaled(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
                                                      _ptr(prod_map), float(n_samples), float(f),
                                                      _ptr(scale), _stream_ptr(stream)),
@@ -130,6 +160,7 @@ def fullcov_inverse_diag(vis: torch.Tensor, autos: torch.Tensor, out: torch.Tens
     F, I, T = _vis_autos(vis, autos)
     if out is None:
         out = torch.empty((F, T, I * I), dtype=torch.float64, device=vis.device)
+    _check_out(out, 8 * F * T * I * I, "qdiag")
     _lib.check(_lib.lib().bsg_fullcov_inverse_diag(_ptr(vis), _ptr(autos), F, I, T, _ptr(out),
                                                     _stream_ptr(stream)), "fullcov_inverse_diag")
     return out
@@ -142,6 +173,7 @@ def round_to_noise_fullcov(vis: torch.Tensor, autos: torch.Tensor, n_samples: fl
     F, I, T = _vis_autos(vis, autos)
     if out is None:
         out = torch.empty_like(vis)
+    _check_out(out, _nbytes(vis), "vis_out")
     _lib.check(_lib.lib().bsg_round_to_noise_fullcov(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
                                                       float(n_samples), float(f),
                                                       _stream_ptr(stream)),
@@ -162,8 +194,8 @@ def round_to_noise_i32(vis: torch.Tensor, autos: torch.Tensor, n_samples: float,
         raise ValueError(f"vis {tuple(vis.shape)} does not match autos {tuple(autos.shape)}")
     if out is None:
         out = torch.empty_like(vis)
-    if prod_map is not None and (prod_map.dtype != torch.int32 or tuple(prod_map.shape) != (vis.shape[1], 2)):
-        raise ValueError("prod_map must be int32 (P, 2)")
+    _check_out(out, _nbytes(vis), "vis_out")
+    _check_prod_map(prod_map, vis.shape[1], I)
     _lib.check(_lib.lib().bsg_round_to_noise_i32(_ptr(vis), _ptr(out), _ptr(autos), F, I, T,
                                                   _ptr(prod_map), float(n_samples), float(f),
                                                   _stream_ptr(stream)), "round_to_noise_i32")
@@ -247,6 +279,7 @@ def compress(x: torch.Tensor, elem_size: int, block_size: int = 0,
     workspace = _alloc_ws(n, elem_size, block_size, x.device, workspace)
     if nbytes is None:
         nbytes = torch.empty(1, dtype=torch.int64, device=x.device)
+    _check_word(nbytes, torch.int64, "nbytes")
     _lib.check(_lib.lib().bsg_compress_lz4_filter(_ptr(x), _ptr(out), n, elem_size, block_size,
                                                    int(filter), _nbytes(out), _ptr(nbytes),
                                                    _ptr(workspace), _nbytes(workspace),
@@ -261,13 +294,15 @@ def round_compress(vis: torch.Tensor, autos: torch.Tensor, n_samples: float, f: 
                    prod_map: torch.Tensor | None = None, stream=None):
     """round_to_noise fused into compress (elem_size 4); vis is not modified."""
     _require_device(vis, autos, out, workspace, nbytes, prod_map)
-    F, I, T = autos.shape
+    F, I, T = _vis_autos(vis, autos)
+    _check_prod_map(prod_map, vis.shape[1], I)
     n = 2 * vis.numel()
     if out is None:
         out = torch.empty(compress_bound(n, 4, block_size), dtype=torch.uint8, device=vis.device)
     workspace = _alloc_ws(n, 4, block_size, vis.device, workspace)
     if nbytes is None:
         nbytes = torch.empty(1, dtype=torch.int64, device=vis.device)
+    _check_word(nbytes, torch.int64, "nbytes")
     _lib.check(_lib.lib().bsg_round_compress_lz4(_ptr(vis), _ptr(autos), F, I, T, _ptr(prod_map),
                                                   float(n_samples), float(f), block_size,
                                                   _ptr(out), _nbytes(out), _ptr(nbytes),
@@ -284,8 +319,12 @@ def decompress(stream_bytes: torch.Tensor, in_nbytes: int, n: int, elem_size: in
     _require_device(stream_bytes, out, status)
     if out is None:
         out = torch.empty(max(n * elem_size, 1), dtype=torch.uint8, device=stream_bytes.device)
+    _check_out(out, n * elem_size, "decompress")
+    if in_nbytes > _nbytes(stream_bytes):
+        raise ValueError("in_nbytes exceeds the stream buffer")
     if status is None:
         status = torch.zeros(1, dtype=torch.int32, device=stream_bytes.device)
+    _check_word(status, torch.int32, "status")
     _lib.check(_lib.lib().bsg_decompress_lz4_filter(_ptr(stream_bytes), int(in_nbytes), _ptr(out),
                                                      n, elem_size, block_size, int(filter),
                                                      _ptr(status), _stream_ptr(stream)),

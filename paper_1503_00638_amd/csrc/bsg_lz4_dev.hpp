@@ -20,11 +20,13 @@ constexpr int kTile = 1024;           // blocks per scan tile
 // of its row of 16 (none: 0); lane 15 (31) feeds the next row (rows 2, 3).
 typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 
-// The codec kernels run one wave per workgroup, and LDS accesses of one wave
-// take effect in program order: between their phases only the compiler must
-// not move memory accesses.  (A workgroup barrier would also wait for every
-// outstanding global load and store of the wave.)
-__device__ __forceinline__ void wave_sync() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+// The codec kernels run one wave per workgroup, and the lanes of a wave hand
+// LDS data to each other between phases: a wavefront-scope fence orders those
+// accesses in the memory model (on gfx950 it emits no instruction, since LDS
+// accesses of one wave complete in order, but no access moves across it).  A
+// workgroup barrier would also wait for every outstanding global load and
+// store of the wave.
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 constexpr int kDppWaveShl1 = 0x130;
 constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;

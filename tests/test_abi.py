@@ -59,6 +59,27 @@ def test_argument_checks_need_no_device(L):
     assert L.bsg_compress_lz4(vp(16), vp(16), 2048, 4, 0, 1 << 20, vp(16), vp(256), 0, None) == -2
 
 
+def test_prod_map_validated_before_any_launch():
+    """A product map with an entry outside [0, I) would make the kernels read
+    the autos out of bounds; the binding refuses it (host tensors here, so no
+    device work is involved)."""
+    import torch
+    import paper_1503_00638_amd as bsg
+    I, P = 4, 10
+    ok = torch.tensor([[i, j] for i in range(I) for j in range(i, I)], dtype=torch.int32)
+    bsg._check_prod_map(ok, P, I)
+    bsg._check_prod_map(None, P, I)
+    for bad in ([[0, 4]], [[-1, 0]], [[0, 2**30]]):
+        m = ok.clone()
+        m[3] = torch.tensor(bad[0], dtype=torch.int32)
+        with pytest.raises(ValueError, match="entries"):
+            bsg._check_prod_map(m, P, I)
+    with pytest.raises(ValueError, match="int32"):
+        bsg._check_prod_map(ok.to(torch.int64), P, I)
+    with pytest.raises(ValueError, match="int32"):
+        bsg._check_prod_map(ok[:5], P, I)
+
+
 def test_read_header(L):
     import numpy as np
     import oracle
