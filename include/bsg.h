@@ -207,6 +207,24 @@ int bsg_compress_lz4(const void *in, void *out, int64_t n, int64_t elem_size,
                      int64_t block_size, int64_t out_capacity, int64_t *d_out_nbytes,
                      void *workspace, int64_t workspace_bytes, void *stream);
 
+/* bsg_compress_lz4 for callers that cannot allocate device memory (code
+ * under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument; the scratch space (block slots, block
+ * sizes, scan tiles) is a fixed array of BSG_NOALLOC_SCRATCH_BYTES inside the
+ * library, one per GPU, held from the library's load until the process
+ * ends.  The call allocates nothing.  It uses the device current on the
+ * calling thread (the stream must belong to it).  Same stream format, bytes,
+ * bounds and errors as bsg_compress_lz4, plus BSG_ECAPACITY when
+ * bsg_compress_workspace_size(n, elem_size, block_size) exceeds
+ * BSG_NOALLOC_SCRATCH_BYTES (at 8192-byte blocks, inputs above about 63 MiB).
+ * Every call on a GPU shares that GPU's array: calls whose work overlaps in
+ * time on one GPU (different streams, or different host threads) race and
+ * must be serialised by the caller. */
+#define BSG_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int bsg_compress_lz4_noalloc(const void *in, void *out, int64_t n, int64_t elem_size,
+                             int64_t block_size, int64_t out_capacity, int64_t *d_out_nbytes,
+                             void *stream);
+
 /* The two stages fused: round_to_noise on complex64 visibilities (arguments
  * as bsg_round_to_noise, vis_in is not modified), then bitshuffle + LZ4 of
  * the rounded values viewed as float32 elements (elem_size 4, n = 2 F P T),

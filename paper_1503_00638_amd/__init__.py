@@ -23,8 +23,10 @@ __all__ = [
     "compress", "round_compress", "decompress", "block_elems", "read_header", "BsgError",
     "compress_sync", "decompress_sync", "BSG_OK", "BSG_EINVAL", "BSG_ECAPACITY",
     "BSG_ECORRUPT", "BSG_EHIP", "load", "BatchPlan", "byteshuffle", "byteunshuffle",
-    "BSG_FILTER_BIT", "BSG_FILTER_BYTE",
+    "BSG_FILTER_BIT", "BSG_FILTER_BYTE", "compress_noalloc", "NOALLOC_SCRATCH_BYTES",
 ]
+
+NOALLOC_SCRATCH_BYTES = _lib.NOALLOC_SCRATCH_BYTES
 
 
 def load():
@@ -285,6 +287,31 @@ def compress(x: torch.Tensor, elem_size: int, block_size: int = 0,
                                                    _ptr(workspace), _nbytes(workspace),
                                                    _stream_ptr(stream)),
                "compress_lz4")
+    return out, nbytes
+
+
+def compress_noalloc(x: torch.Tensor, elem_size: int, block_size: int = 0,
+                     out: torch.Tensor | None = None, nbytes: torch.Tensor | None = None,
+                     stream=None):
+    """compress (bit transpose + LZ4) through the entry point that allocates
+    nothing: the scratch space is the library's fixed per-GPU array, so inputs
+    whose workspace_size exceeds NOALLOC_SCRATCH_BYTES are refused.  Calls
+    that overlap in time on one GPU race on that array."""
+    _require_device(x, out, nbytes)
+    total = _nbytes(x)
+    if total % elem_size:
+        raise ValueError("buffer is not a whole number of elements")
+    n = total // elem_size
+    if out is None:
+        out = torch.empty(compress_bound(n, elem_size, block_size), dtype=torch.uint8,
+                          device=x.device)
+    if nbytes is None:
+        nbytes = torch.empty(1, dtype=torch.int64, device=x.device)
+    _check_word(nbytes, torch.int64, "nbytes")
+    _lib.check(_lib.lib().bsg_compress_lz4_noalloc(_ptr(x), _ptr(out), n, elem_size, block_size,
+                                                    _nbytes(out), _ptr(nbytes),
+                                                    _stream_ptr(stream)),
+               "compress_lz4_noalloc")
     return out, nbytes
 
 

@@ -27,8 +27,9 @@ EXPORTS = (
     "bsg_batch_compress", "bsg_batch_decompress", "bsg_round_to_noise_i32",
     "bsg_noise_compensation", "bsg_round_to_noise_scaled", "bsg_byteshuffle",
     "bsg_byteunshuffle", "bsg_compress_lz4_filter", "bsg_decompress_lz4_filter",
-    "bsg_fullcov_inverse_diag", "bsg_round_to_noise_fullcov",
+    "bsg_fullcov_inverse_diag", "bsg_round_to_noise_fullcov", "bsg_compress_lz4_noalloc",
 )
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Header(ctypes.Structure):
@@ -88,6 +89,8 @@ def _lib():
         L.bsg_compress_workspace_size.restype = i64
         L.bsg_compress_lz4.argtypes = [vp, vp, i64, i64, i64, i64, vp, vp, i64, vp]
         L.bsg_compress_lz4.restype = i32
+        L.bsg_compress_lz4_noalloc.argtypes = [vp, vp, i64, i64, i64, i64, vp, vp]
+        L.bsg_compress_lz4_noalloc.restype = i32
         L.bsg_round_compress_lz4.argtypes = [vp, vp, i64, i64, i64, vp, dbl, dbl, i64, vp, i64,
                                              vp, vp, i64, vp]
         L.bsg_round_compress_lz4.restype = i32

@@ -2,6 +2,7 @@
 // launches on the caller's stream.  Nothing here allocates device memory.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "bsg_internal.hpp"
 
@@ -69,6 +70,32 @@ inline RoundParams make_round(const float *autos, const int32_t *prod_map, int64
 inline int64_t fixed_stream_bytes(const Layout &L)
 {
     return kHeaderBytes + 8 * (L.n_blocks + 1) + L.tail * L.E;
+}
+
+// Compression scratch space for callers that cannot allocate: one array of
+// fixed size in every GPU's copy of the code object.  In host code its name
+// only stands for the symbol; the device address of each GPU's copy comes
+// from hipGetSymbolAddress, made once per device with that device current.
+__device__ __align__(256) uint8_t scratch[BSG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices]; // guarded by scratch_mu
+
+// Device address of the current device's scratch array.
+int scratch_for_current_device(void **ptr)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return BSG_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return BSG_EINVAL;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BSG_EHIP;
+        scratch_ptr[dev] = p;
+    }
+    *ptr = scratch_ptr[dev];
+    return BSG_OK;
 }
 
 } // namespace
@@ -268,6 +295,24 @@ int bsg_compress_lz4(const void *in, void *out, int64_t n, int64_t elem_size, in
     if (!make_layout(n, elem_size, block_size, &L)) return BSG_EINVAL;
     return compress_common(in, out, L, out_capacity, d_out_nbytes, workspace, workspace_bytes,
                            nullptr, stream);
+}
+
+int bsg_compress_lz4_noalloc(const void *in, void *out, int64_t n, int64_t elem_size,
+                             int64_t block_size, int64_t out_capacity, int64_t *d_out_nbytes,
+                             void *stream)
+{
+    Layout L;
+    if (!make_layout(n, elem_size, block_size, &L)) return BSG_EINVAL;
+    if (L.block_bytes() > BSG_MAX_BLOCK_BYTES) return BSG_EINVAL;
+    // every part of the scratch space is written before it is read, so the
+    // previous call's contents need no clearing
+    if (compress_workspace(L) > (int64_t)BSG_NOALLOC_SCRATCH_BYTES) return BSG_ECAPACITY;
+    if (!out || !d_out_nbytes || (L.n > 0 && !in)) return BSG_EINVAL;
+    void *ws = nullptr;
+    const int st = scratch_for_current_device(&ws);
+    if (st != BSG_OK) return st;
+    return compress_common(in, out, L, out_capacity, d_out_nbytes, ws,
+                           (int64_t)BSG_NOALLOC_SCRATCH_BYTES, nullptr, stream);
 }
 
 int bsg_compress_lz4_filter(const void *in, void *out, int64_t n, int64_t elem_size,

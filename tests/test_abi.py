@@ -59,6 +59,20 @@ def test_argument_checks_need_no_device(L):
     assert L.bsg_compress_lz4(vp(16), vp(16), 2048, 4, 0, 1 << 20, vp(16), vp(256), 0, None) == -2
 
 
+def test_noalloc_argument_checks(L):
+    """The entry point that allocates nothing refuses, on the host, inputs
+    whose scratch space would exceed its fixed array, and bad block sizes."""
+    from paper_1503_00638_amd import _lib
+    vp = ctypes.c_void_p
+    big = _lib.NOALLOC_SCRATCH_BYTES // 4 + (1 << 20)  # float32 elements
+    assert L.bsg_compress_workspace_size(big, 4, 2048) > _lib.NOALLOC_SCRATCH_BYTES
+    assert L.bsg_compress_lz4_noalloc(vp(4096), vp(8192), big, 4, 2048, 1 << 40, vp(16), None) == -2
+    assert L.bsg_compress_lz4_noalloc(vp(4096), vp(8192), 100, 4, 12, 1 << 20, vp(16), None) == -1
+    assert L.bsg_compress_lz4_noalloc(vp(4096), vp(8192), 100, 4, 1 << 16, 1 << 20, vp(16), None) == -1
+    fits = L.bsg_compress_workspace_size((60 << 20) // 4, 4, 2048)
+    assert 0 < fits <= _lib.NOALLOC_SCRATCH_BYTES
+
+
 def test_prod_map_validated_before_any_launch():
     """A product map with an entry outside [0, I) would make the kernels read
     the autos out of bounds; the binding refuses it (host tensors here, so no
