@@ -193,7 +193,7 @@ int64_t bsg_compress_workspace_size(int64_t n, int64_t elem_size, int64_t block_
  * (hash of 4 bytes, 10 bits, Knuth's multiplier 2654435761; candidate = the
  * last earlier position with that hash in an earlier 64-position chunk; the
  * candidate is extended forward only, keeping the last 5 bytes literal, and
- * taken when it covers at least 8 bytes starting at p <= len - 12), so the
+ * taken when it covers at least 12 bytes starting at p <= len - 12), so the
  * output bytes are a pure function of the input.  The result is a standard
  * LZ4 block that any LZ4 decoder reads.
  * out: out_capacity bytes.  *d_out_nbytes (device int64) receives the

@@ -27,7 +27,7 @@
 #define HASH_MULT 2654435761u /* Knuth's multiplicative constant */
 #define CHUNK 64             /* candidate table is updated every 64 positions */
 #define MINMATCH 4       /* LZ4 format: match lengths are coded as length - 4 */
-#define MINTAKE 8        /* the rule only takes matches of at least 8 bytes */
+#define MINTAKE 12       /* the rule only takes matches of at least 12 bytes */
 #define MFLIMIT 12       /* a match may start only at p <= n - 12 */
 #define LASTLITERALS 5   /* the last 5 bytes of a block are literals */
 
@@ -763,7 +763,7 @@ int64_t oracle_lz4_compress_block(const uint8_t *x, int64_t n, uint8_t *dst, int
 
     /* Greedy parse: at p, extend the candidate forward only (no backward
      * extension, no lazy evaluation) while keeping the last 5 bytes as
-     * literals; the match is taken when it covers at least 8 bytes, else p
+     * literals; the match is taken when it covers at least 12 bytes, else p
      * moves on by one byte. */
     int64_t op = 0, anchor = 0, p = 0;
     while (p <= last_start) {

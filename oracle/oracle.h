@@ -86,7 +86,7 @@ int oracle_bitunshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem
 /* One LZ4 block with the fixed greedy rule: 10-bit multiplicative hash of
  * 4 bytes, candidate = the last earlier position with that hash in an
  * earlier 64-position chunk, forward extension only (the last 5 bytes stay
- * literal), a match taken when it covers at least 8 bytes and starts at
+ * literal), a match taken when it covers at least 12 bytes and starts at
  * p <= n - 12.  Returns the compressed size, or -2 when cap is too small. */
 int64_t oracle_lz4_compress_block(const uint8_t *src, int64_t n, uint8_t *dst, int64_t cap);
 

@@ -22,7 +22,7 @@ constexpr int kHashBits = 10;
 constexpr uint32_t kHashMult = 2654435761u;
 constexpr int kChunk = 64;       // the candidate table is updated per 64 positions
 constexpr int kMinMatch = 4;     // LZ4 codes match lengths as length - 4
-constexpr int kMinTake = 8;      // the rule takes matches of >= 8 bytes only
+constexpr int kMinTake = 12;     // the rule takes matches of >= 12 bytes only
 constexpr int kMfLimit = 12;     // a match starts at p <= len - 12
 constexpr int kLastLiterals = 5; // the last 5 bytes are literals
 constexpr int kGroup = 512;      // positions hashed before each parse step (8 chunks)

@@ -358,7 +358,7 @@ __device__ __forceinline__ int extend_match(const uint32_t *b32, int c, int q, i
 // Per group of 512 positions: (1) read the 4 bytes at every position, (2)
 // per 64-position chunk read the table entry of every position, then raise
 // the entries to the chunk's positions (the wave's in-order LDS queue makes
-// chunk c see exactly chunks < c), (3) verify 8 bytes at every candidate of
+// chunk c see exactly chunks < c), (3) verify 12 bytes at every candidate of
 // a chunk the parse enters, (4) parse greedily with the candidates in VGPRs
 // and the match masks in SGPRs.
 // Hash and insert the kGroup positions from g0 (the fixed rule of the LZ4
@@ -426,7 +426,7 @@ __device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table,
 }
 
 // The mask of the chunk's positions (from c0, a multiple of 64) whose
-// candidate matches for 8 bytes and may be taken (<= last_take).
+// candidate matches for kMinTake = 12 bytes and may be taken (<= last_take).
 // Branch-free: a lane without a candidate reads position 0 and is masked
 // after.
 __device__ __forceinline__ uint64_t verify_chunk(const uint32_t *b32, int c0, uint32_t cand,
@@ -437,13 +437,15 @@ __device__ __forceinline__ uint64_t verify_chunk(const uint32_t *b32, int c0, ui
     const int c = cn != 0 ? (int)cn - 1 : 0;
     const uint32_t *o = b32 + (p >> 2);
     const uint32_t *d = b32 + (c >> 2);
-    const uint32_t o0 = o[0], o1 = o[1], o2 = o[2];
-    const uint32_t e0 = d[0], e1 = d[1], e2 = d[2];
-    // zero when the candidate exists and its 8 bytes equal those at p
+    const uint32_t o0 = o[0], o1 = o[1], o2 = o[2], o3 = o[3];
+    const uint32_t e0 = d[0], e1 = d[1], e2 = d[2], e3 = d[3];
+    // zero when the candidate exists and its 12 bytes equal those at p
     const uint32_t x = (__builtin_amdgcn_alignbyte(e1, e0, (uint32_t)(c & 3)) ^
                         __builtin_amdgcn_alignbyte(o1, o0, (uint32_t)(p & 3))) |
                        (__builtin_amdgcn_alignbyte(e2, e1, (uint32_t)(c & 3)) ^
                         __builtin_amdgcn_alignbyte(o2, o1, (uint32_t)(p & 3))) |
+                       (__builtin_amdgcn_alignbyte(e3, e2, (uint32_t)(c & 3)) ^
+                        __builtin_amdgcn_alignbyte(o3, o2, (uint32_t)(p & 3))) |
                        ((cn - 1u) >> 31);
     return __ballot(x == 0);
 }
@@ -467,7 +469,8 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
     wave_sync();
 
     const int last_q = n - kMfLimit;           // last position a match may start at
-    const int last_take = last_q - 1;          // ... and still reach 8 bytes
+    const int last_take = last_q - (kMinTake - 7); // ... and still reach kMinTake bytes
+                                                   // before the last 5 literals
     const int last_ins = n - kMinMatch;        // last position with a defined hash
     int anchor = 0, pnext = 0, op = 0;
     // sequences found and not yet written: lane j holds sequence j
@@ -617,6 +620,36 @@ __device__ __forceinline__ void dcopy(uint32_t *b32, int op, int src, int len)
         dcopy_step(b32, b + (int)threadIdx.x, delta, sh, op, end);
 }
 
+// Two adjacent copies in one pass: out[a, b) = buf[a + d1, b + d1) (a match
+// whose source ends at or before a: d1 = -off, off >= b - a) and
+// out[b, c) = buf[b + d2, c + d2) (literals, d2 >= 0).  Both are
+// independent of each other's output, so each lane builds its dword from
+// both sources: the match bytes under the mask of [a, b), the literal bytes
+// under the rest of the mask of [a, c) (both masks are valid for every dword
+// from a / 4 on, so no lane branches).  Same padding and ordering rules as
+// dcopy.
+__device__ __forceinline__ void dcopy2_step(uint32_t *b32, int w, int d1, uint32_t sh1, int d2,
+                                            uint32_t sh2, int a, int b, int c)
+{
+    const uint32_t old = b32[w];
+    const int s1 = (4 * w + d1) >> 2, s2 = (4 * w + d2) >> 2;
+    const uint32_t v1 = __builtin_amdgcn_alignbyte(b32[s1 + 1], b32[s1], sh1);
+    const uint32_t v2 = __builtin_amdgcn_alignbyte(b32[s2 + 1], b32[s2], sh2);
+    const uint32_t m1 = range_mask(4 * w, a, b);
+    const uint32_t mall = range_mask(4 * w, a, c);
+    const uint32_t v = (v1 & m1) | (v2 & ~m1);
+    b32[w] = (v & mall) | (old & ~mall);
+}
+
+__device__ __forceinline__ void dcopy2(uint32_t *b32, int a, int d1, int b, int d2, int c)
+{
+    const int w0 = a >> 2, w1 = (c + 3) >> 2;
+    const uint32_t sh1 = (uint32_t)(d1 & 3), sh2 = (uint32_t)(d2 & 3);
+    dcopy2_step(b32, w0 + (int)threadIdx.x, d1, sh1, d2, sh2, a, b, c);
+    for (int k = w0 + kWave; k < w1; k += kWave)
+        dcopy2_step(b32, k + (int)threadIdx.x, d1, sh1, d2, sh2, a, b, c);
+}
+
 // One wave step of an overlapping match, for dword w (r: the byte offset of
 // the dword's first byte from op, mod off).  Period 1..3: the dword is built
 // from the period's bytes p0..p2.
@@ -706,77 +739,112 @@ __device__ __forceinline__ void dmatch(uint32_t *b32, int op, int off, int len)
 // sequence, and the output may never reach input not yet read.
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// The bytes from position pos of the buffer as a wave-uniform little-endian
+// 64-bit value (byte pos in bits 0-7): the two dwords holding pos, so at
+// least the 5 bytes pos .. pos + 4 are valid.
+__device__ __forceinline__ uint64_t lds_le64_uni(const uint32_t *b32, int pos)
+{
+    const int a = pos >> 2;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)b32[a]);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)b32[a + 1]);
+    return ((uint64_t)hi << 32 | lo) >> (8 * (pos & 3));
+}
+
+// The head of a sequence from its token at ip (w: the token and the bytes
+// after it): the literal length and the literals' position.  A length field
+// whose continuation runs past the input gives a length that fails every
+// check.
+__device__ __forceinline__ void seq_head(const uint8_t *b8, int ip, uint64_t w, int iend, int &ll,
+                                         int &lit)
+{
+    constexpr int kBadLength = 1 << 30;
+    ll = (int)(((uint32_t)w & 255u) >> 4);
+    lit = ip + 1;
+    if (ll == 15) {
+        const int e = (int)((uint32_t)(w >> 8) & 255u);
+        if (e != 255) {
+            ll += e;
+            lit = ip + 2;
+        } else {
+            int q = ip + 1;
+            if (!read_len_ext(b8, q, iend, ll)) ll = kBadLength;
+            lit = uni(q);
+            ll = uni(ll);
+        }
+    }
+}
+
 __device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend, int ob)
 {
-    // A length that fails every check below: a length field whose
-    // continuation runs past the input is reported through it, so each
-    // sequence has only three exits (bad literals, end of block, bad match).
     constexpr int kBadLength = 1 << 30;
     uint8_t *b8 = reinterpret_cast<uint8_t *>(b32);
     int ip = uni(ip0), op = 0;
     iend = uni(iend);
     ob = uni(ob);
-    uint32_t w = __builtin_amdgcn_readfirstlane(lds_le32(b32, ip));
-    for (;;) {
-        ip = uni(ip);
-        op = uni(op);
-        w = (uint32_t)uni((int)w);
-        const uint32_t tok = w & 255u;
-        int ll = (int)(tok >> 4);
-        int lit = ip + 1;
-        if (ll == 15) {
-            const int e = (int)((w >> 8) & 255u);
-            if (e != 255) {
-                ll += e;
-                lit = ip + 2;
-            } else {
-                int q = ip + 1;
-                if (!read_len_ext(b8, q, iend, ll)) ll = kBadLength;
-                lit = uni(q);
-                ll = uni(ll);
-            }
-        }
-        ll = uni(ll);
-        lit = uni(lit);
-        // token, length bytes and literals inside the input (lit + ll <= iend
-        // also puts the length bytes before iend); output inside the block and
-        // never past unread input
-        // (all quantities are far below 2^31: a check fails iff its difference
-        // is negative, so one sign test covers them all)
-        if (((iend - 1 - ip) | (iend - lit - ll) | (ob - op - ll) | (lit - op)) < 0) return false;
-        const int ip2 = lit + ll;
-        uint32_t ow = lds_le32(b32, ip2); // offset and first length byte
-        dcopy(b32, op, lit, ll);
-        op += ll;
-        if (ip2 == iend) break;
-        ow = __builtin_amdgcn_readfirstlane(ow);
-        const int off = (int)(ow & 0xFFFFu);
+    if (ip >= iend) return false; // not even a token
+    // Sequence j's match and sequence j + 1's literals are adjacent in the
+    // output and independent of each other, so they are copied in one pass
+    // (unless the match overlaps its own output).  The input past each
+    // literal run is read once: offset, a match-length byte, the next token
+    // and its first length byte.
+    uint64_t w = lds_le64_uni(b32, ip);
+    uint32_t tok = (uint32_t)w & 255u;
+    int ll, lit;
+    seq_head(b8, ip, w, iend, ll, lit);
+    // literals (and so the length bytes) inside the input; output inside the
+    // block and never past unread input.  All quantities are far below 2^31:
+    // a check fails iff its difference is negative, so one sign test covers
+    // them all.
+    if (((iend - lit - ll) | (ob - ll) | lit) < 0) return false;
+    int ip2 = lit + ll;
+    int ipr = ip2 < iend ? ip2 : iend;
+    uint32_t r0 = b32[ipr >> 2], r1 = b32[(ipr >> 2) + 1];
+    dcopy(b32, 0, lit, ll);
+    op = ll;
+    while (ip2 != iend) {
+        const uint64_t ow = ((uint64_t)(uint32_t)uni((int)r1) << 32 | (uint32_t)uni((int)r0)) >>
+                            (8 * (ipr & 3));
+        const int off = (int)((uint32_t)ow & 0xFFFFu);
         int ml = (int)(tok & 15u) + kMinMatch;
         int nip = ip2 + 2;
+        uint64_t nw = ow >> 16;
         if ((tok & 15u) == 15u) {
-            const int e = (int)((ow >> 16) & 255u);
+            const int e = (int)((uint32_t)(ow >> 16) & 255u);
             if (e != 255) {
                 ml += e;
                 nip = ip2 + 3;
+                nw = ow >> 24;
             } else {
                 int q = ip2 + 2;
                 if (!read_len_ext(b8, q, iend, ml)) ml = kBadLength;
                 nip = uni(q);
                 ml = uni(ml);
+                nw = lds_le64_uni(b32, nip < iend ? nip : iend);
             }
         }
-        ml = uni(ml);
-        nip = uni(nip);
         // offset and length bytes inside the input with a token after them
         // (nip < iend), offset into the output so far, output inside the
         // block and never past unread input
         if (((iend - 1 - nip) | (off - 1) | (op - off) | (ob - op - ml) | (nip - op - ml)) < 0)
             return false;
-        w = lds_le32(b32, nip); // next token, read together with the match source
-        dmatch(b32, op, off, ml);
-        w = __builtin_amdgcn_readfirstlane(w);
-        op += ml;
-        ip = nip;
+        // the next sequence's head (its input lies at or past nip, which the
+        // match does not reach)
+        const int op2 = op + ml;
+        tok = (uint32_t)nw & 255u;
+        int ll2, lit2;
+        seq_head(b8, nip, nw, iend, ll2, lit2);
+        if (((iend - lit2 - ll2) | (ob - op2 - ll2) | (lit2 - op2)) < 0) return false;
+        ip2 = lit2 + ll2;
+        ipr = ip2 < iend ? ip2 : iend;
+        r0 = b32[ipr >> 2];
+        r1 = b32[(ipr >> 2) + 1];
+        if (off >= ml) {
+            dcopy2(b32, op, -off, op2, lit2 - op2, op2 + ll2);
+        } else {
+            dmatch(b32, op, off, ml);
+            dcopy(b32, op2, lit2, ll2);
+        }
+        op = op2 + ll2;
     }
     return op == ob;
 }

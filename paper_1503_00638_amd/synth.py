@@ -175,8 +175,8 @@ def gen_walk_int16(n: int, seed: int) -> np.ndarray:
     return (np.cumsum(steps) & 0xFFFF).astype(np.uint16).view(np.int16)
 
 
-def gen_short_matches(nbytes: int, seed: int, lit_max: int = 4, match_lo: int = 8,
-                      match_hi: int = 14, window: int = 600) -> np.ndarray:
+def gen_short_matches(nbytes: int, seed: int, lit_max: int = 4, match_lo: int = 12,
+                      match_hi: int = 18, window: int = 600) -> np.ndarray:
     """Bytes built as an LZ77 source: runs of 0..lit_max random literals, each
     followed by a copy of match_lo..match_hi bytes from up to `window` bytes
     back.  An 8 KiB block of it parses into hundreds of short sequences."""

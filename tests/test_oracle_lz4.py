@@ -13,6 +13,7 @@ from paper_1503_00638_amd import synth
 pytestmark = pytest.mark.skipif(not lz4ref.available(), reason="system liblz4 not present")
 
 HASH_BITS, CHUNK, MULT = 10, 64, 2654435761
+MIN_TAKE = 12  # shortest match the rule takes
 
 
 def le32(x, q):
@@ -26,7 +27,7 @@ def h(x, q):
 def brute_encode(x: bytes) -> bytes:
     """The fixed rule stated directly: cand(p) = largest q <= n-4 with
     q // 64 < p // 64 and h(q) == h(p), found by scanning every q; a match
-    is taken when it extends to at least 8 bytes."""
+    is taken when it extends to at least MIN_TAKE bytes."""
     n = len(x)
 
     def cand(p):
@@ -56,7 +57,7 @@ def brute_encode(x: bytes) -> bytes:
         if c is not None:
             while p + L < n - 5 and x[c + L] == x[p + L]:
                 L += 1
-        if L >= 8:
+        if L >= MIN_TAKE:
             lits(anchor, p, min(L - 4, 15))
             out.extend(((p - c) & 255, (p - c) >> 8))
             if L - 4 >= 15:
@@ -84,9 +85,9 @@ def structured_blocks(rng):
     yield rng.integers(0, 256, 300, dtype=np.uint8).tobytes()
     yield rng.integers(0, 4, 400, dtype=np.uint8).tobytes()
     yield (b"abcdefgh" * 60)[:450]
-    # matches of exactly 7, 8 and 9 bytes around the acceptance threshold
+    # matches of one byte below, at and above the acceptance threshold
     base = bytes(rng.integers(0, 256, 64, dtype=np.uint8))
-    for k in (7, 8, 9):
+    for k in (MIN_TAKE - 1, MIN_TAKE, MIN_TAKE + 1):
         yield base + base[:k] + bytes(rng.integers(0, 256, 40, dtype=np.uint8)) + base[3:3 + k] + bytes(20)
     pat = rng.integers(0, 256, 70, dtype=np.uint8).tobytes()
     yield pat * 5 + rng.integers(0, 256, 30, dtype=np.uint8).tobytes() + pat * 2
@@ -104,11 +105,12 @@ def test_brute_force_rule(oracle_lib):
 def test_all_zero_closed_form(oracle_lib):
     """Positions 0..63 have no candidate (chunk 0); p = 64 matches q = 63 at
     offset 1 and extends to n - 5; then 5 literals close the block.  The
-    match is taken only when it covers at least 8 bytes (n >= 77); below
-    that the whole block is one literal run."""
-    got = oracle_lib.lz4_compress_block(np.zeros(76, np.uint8))
-    assert got == bytes([0xF0, 76 - 15]) + bytes(76)
-    for n in (77, 200, 4096, 8192, 65536):
+    match is taken only when it covers at least MIN_TAKE bytes
+    (n >= 69 + MIN_TAKE); below that the whole block is one literal run."""
+    n0 = 69 + MIN_TAKE
+    got = oracle_lib.lz4_compress_block(np.zeros(n0 - 1, np.uint8))
+    assert got == bytes([0xF0, n0 - 1 - 15]) + bytes(n0 - 1)
+    for n in (n0, 200, 4096, 8192, 65536):
         got = oracle_lib.lz4_compress_block(np.zeros(n, np.uint8))
         L = n - 5 - 64
         exp = bytearray([0xF0 | min(L - 4, 15), 64 - 15]) + bytes(64) + bytes([1, 0])
