@@ -333,23 +333,24 @@ def bench_batch(args, torch, bsg):
 
     plan_c = bsg.BatchPlan.for_compress(xs, Es, Bs)
     wc, tune_c = tune.tune(plan_c, "compress", use_cache=False)
-    nb = plan_c.compress(wc).cpu().numpy().copy()
+    nb = plan_c.compress(*wc).cpu().numpy().copy()
     assert (nb > 0).all()
     plan_d = bsg.BatchPlan.for_decompress(plan_c.outs, nb.tolist(), ns, Es, Bs)
     wd, tune_d = tune.tune(plan_d, "decompress", use_cache=False)
-    st = plan_d.decompress(wd)
+    st = plan_d.decompress(*wd)
     torch.cuda.synchronize()
     assert not st.any().item()
     for x, y, s in zip(xs, plan_d.outs, specs):
         assert torch.equal(x, y[: s.nbytes]), f"round trip mismatch in chunk {s.index}"
-    print(f"# tuned waves/CU: compress {wc}, decompress {wd}", file=sys.stderr, flush=True)
+    print(f"# tuned (waves/CU, schedule): compress {wc}, decompress {wd}", file=sys.stderr,
+          flush=True)
 
     gc, gd = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
     torch.cuda.synchronize()
     with torch.cuda.graph(gc):
-        plan_c.compress(wc)
+        plan_c.compress(*wc)
     with torch.cuda.graph(gd):
-        plan_d.decompress(wd)
+        plan_d.decompress(*wd)
     comp_ms = _time_calls(torch, gc.replay, args.steps, args.warmup)
     dec_ms = _time_calls(torch, gd.replay, args.steps, args.warmup)
     assert np.array_equal(plan_c.nbytes.cpu().numpy(), nb) and not plan_d.status.any().item()
@@ -413,7 +414,8 @@ def bench_batch(args, torch, bsg):
                        "compress_p99": round(float(np.percentile(comp_ms, 99)), 3),
                        "decompress_p50": round(float(np.percentile(dec_ms, 50)), 3),
                        "decompress_p99": round(float(np.percentile(dec_ms, 99)), 3)},
-        "autotune": {"waves_per_cu": {"compress": wc, "decompress": wd},
+        "autotune": {"knobs": "waves_per_cu,schedule (0 strided, 1 contiguous ranges)",
+                     "best": {"compress": list(wc), "decompress": list(wd)},
                      "compress_ms": {str(k): round(v, 3) for k, v in tune_c.items()},
                      "decompress_ms": {str(k): round(v, 3) for k, v in tune_d.items()}},
         "per_chunk_eager": {"compress_GBps": gbps(float(np.median(pcc_ms))),

@@ -287,18 +287,26 @@ int bsg_batch_build_table(const bsg_chunk *chunks, int32_t count, void *host_tab
 /* Device workspace bytes bsg_batch_compress needs for this table. */
 int64_t bsg_batch_workspace_size(const void *host_table);
 
+/* Launch shape of the persistent batch kernels (it never changes the
+ * output): waves_per_cu = workgroups per compute unit in the grid (<= 0:
+ * 16; one wavefront per workgroup, one block at a time); schedule = how the
+ * blocks of a class are dealt to the workgroups: BSG_SCHED_STRIDED, every
+ * grid-th block from the workgroup's index, or BSG_SCHED_RANGES, one
+ * contiguous range of blocks per workgroup. */
+#define BSG_SCHED_STRIDED 0
+#define BSG_SCHED_RANGES 1
+
 /* Compress every chunk of the table.  d_nbytes: device int64[count],
  * entry i (the caller's chunk order) receives chunk i's stream length, or
  * BSG_ECAPACITY when it would exceed that chunk's out_capacity (then its
  * out holds nothing meaningful; the other chunks are unaffected).
  * workspace: 256-byte aligned, workspace_bytes >= bsg_batch_workspace_size.
- * waves_per_cu: resident workgroups per compute unit of the persistent
- *   kernels (<= 0: 16).
- * Errors: BSG_EINVAL (NULL pointers, misaligned buffers), BSG_ECAPACITY
- *   (workspace too small), BSG_EHIP (launch failure). */
+ * waves_per_cu, schedule: the launch shape (above).
+ * Errors: BSG_EINVAL (NULL pointers, misaligned buffers, unknown schedule),
+ *   BSG_ECAPACITY (workspace too small), BSG_EHIP (launch failure). */
 int bsg_batch_compress(const void *host_table, const void *d_table, int64_t *d_nbytes,
                        void *workspace, int64_t workspace_bytes, int32_t waves_per_cu,
-                       void *stream);
+                       int32_t schedule, void *stream);
 
 /* Decompress every chunk of the table (streams from bsg_compress_lz4 or
  * bsg_batch_compress, or any valid LZ4 encoding of their blocks).
@@ -306,7 +314,7 @@ int bsg_batch_compress(const void *host_table, const void *d_table, int64_t *d_n
  * and receives BSG_ECORRUPT when chunk i's stream is invalid, with the same
  * checks and the same memory bounds as bsg_decompress_lz4. */
 int bsg_batch_decompress(const void *host_table, const void *d_table, int32_t *d_status,
-                         int32_t waves_per_cu, void *stream);
+                         int32_t waves_per_cu, int32_t schedule, void *stream);
 
 /* bsg_compress_lz4 / bsg_decompress_lz4 with the block filter chosen by
  * `filter` (BSG_FILTER_BIT gives exactly those calls; BSG_FILTER_BYTE

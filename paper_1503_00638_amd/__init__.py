@@ -15,7 +15,8 @@ import torch
 
 from . import _lib
 from ._lib import (BSG_ECAPACITY, BSG_ECORRUPT, BSG_EHIP, BSG_EINVAL, BSG_FILTER_BIT,
-                   BSG_FILTER_BYTE, BSG_OK, BsgError, Header)
+                   BSG_FILTER_BYTE, BSG_OK, BSG_SCHED_RANGES, BSG_SCHED_STRIDED, BsgError,
+                   Header)
 
 __all__ = [
     "round_to_noise", "round_to_noise_i32", "noise_compensation", "round_to_noise_scaled",
@@ -24,6 +25,7 @@ __all__ = [
     "compress_sync", "decompress_sync", "BSG_OK", "BSG_EINVAL", "BSG_ECAPACITY",
     "BSG_ECORRUPT", "BSG_EHIP", "load", "BatchPlan", "byteshuffle", "byteunshuffle",
     "BSG_FILTER_BIT", "BSG_FILTER_BYTE", "compress_noalloc", "NOALLOC_SCRATCH_BYTES",
+    "BSG_SCHED_STRIDED", "BSG_SCHED_RANGES",
 ]
 
 NOALLOC_SCRATCH_BYTES = _lib.NOALLOC_SCRATCH_BYTES
@@ -458,22 +460,27 @@ class BatchPlan:
             plan.status = torch.zeros(max(k, 1), dtype=torch.int32, device=device)
         return plan
 
-    def compress(self, waves_per_cu: int = 0, stream=None) -> torch.Tensor:
-        """Enqueue; returns the device int64 stream lengths (caller's order)."""
+    def compress(self, waves_per_cu: int = 0, schedule: int = BSG_SCHED_STRIDED,
+                 stream=None) -> torch.Tensor:
+        """Enqueue; returns the device int64 stream lengths (caller's order).
+        waves_per_cu and schedule set the launch shape (never the bytes)."""
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         _lib.check(_lib.lib().bsg_batch_compress(self._host, _ptr(self._dev), _ptr(self.nbytes),
                                                   _ptr(self.workspace), _nbytes(self.workspace),
-                                                  waves_per_cu, _stream_ptr(st)),
+                                                  int(waves_per_cu), int(schedule),
+                                                  _stream_ptr(st)),
                    "batch_compress")
         return self.nbytes
 
-    def decompress(self, waves_per_cu: int = 0, stream=None) -> torch.Tensor:
+    def decompress(self, waves_per_cu: int = 0, schedule: int = BSG_SCHED_STRIDED,
+                   stream=None) -> torch.Tensor:
         """Enqueue; returns the device int32 per-chunk status (0 = ok)."""
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.stream(st):
             self.status.zero_()
         _lib.check(_lib.lib().bsg_batch_decompress(self._host, _ptr(self._dev), _ptr(self.status),
-                                                    waves_per_cu, _stream_ptr(st)),
+                                                    int(waves_per_cu), int(schedule),
+                                                    _stream_ptr(st)),
                    "batch_decompress")
         return self.status
 

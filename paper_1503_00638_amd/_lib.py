@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_PKG, "libbsg.so")
 
 BSG_OK = 0
 BSG_FILTER_BIT, BSG_FILTER_BYTE = 0, 1
+BSG_SCHED_STRIDED, BSG_SCHED_RANGES = 0, 1
 BSG_EINVAL = -1
 BSG_ECAPACITY = -2
 BSG_ECORRUPT = -3
@@ -109,9 +110,9 @@ def _lib():
         L.bsg_batch_build_table.restype = i32
         L.bsg_batch_workspace_size.argtypes = [vp]
         L.bsg_batch_workspace_size.restype = i64
-        L.bsg_batch_compress.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, vp]
+        L.bsg_batch_compress.argtypes = [vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_int32, vp]
         L.bsg_batch_compress.restype = i32
-        L.bsg_batch_decompress.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+        L.bsg_batch_decompress.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp]
         L.bsg_batch_decompress.restype = i32
         _LIB = L
     return _LIB

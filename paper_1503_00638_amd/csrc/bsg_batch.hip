@@ -77,17 +77,58 @@ __device__ __forceinline__ int find_chunk(const BatchChunk *ch, int lo, int hi, 
     return lo;
 }
 
+// The blocks of a class that one workgroup of a persistent launch takes, in
+// increasing order: every gridDim.x-th block from blockIdx.x
+// (BSG_SCHED_STRIDED), or one contiguous range of ceil(n / gridDim.x) blocks
+// (BSG_SCHED_RANGES).  Either way every block is taken by exactly one
+// workgroup, so the output does not depend on the schedule.
+struct BlockWalk {
+    int64_t first, end, step;
+    __device__ BlockWalk(const BatchClass &C, int schedule)
+    {
+        const int64_t n = C.n_blocks;
+        if (schedule == BSG_SCHED_RANGES) {
+            const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+            const int64_t lo = (int64_t)blockIdx.x * per < n ? (int64_t)blockIdx.x * per : n;
+            first = C.first_block + lo;
+            end = C.first_block + (lo + per < n ? lo + per : n);
+            step = 1;
+        } else {
+            first = C.first_block + blockIdx.x;
+            end = C.first_block + n;
+            step = gridDim.x;
+        }
+    }
+};
+
+// The chunk owning block g, given the chunk c of an earlier block of the
+// same walk (blocks only grow): under the range schedule the walk steps
+// through the table, one read per block; under the strided one it searches
+// the rest of the table.
+__device__ __forceinline__ int next_chunk(const BatchChunk *ch, int c, int last, int64_t g,
+                                          int64_t step)
+{
+    if (step == 1) {
+        while (c < last && ch[c + 1].block_start <= g) ++c;
+        return c;
+    }
+    return find_chunk(ch, c, last, g);
+}
+
 template <int MAXB, int EC>
 __global__ __launch_bounds__(64) void k_batch_encode(const uint8_t *__restrict__ table, int cls,
                                                      uint8_t *__restrict__ slots,
-                                                     int32_t *__restrict__ sizes)
+                                                     int32_t *__restrict__ sizes, int schedule)
 {
     __shared__ EncLds<MAXB> L;
     const TableView T(table);
     const BatchClass C = T.cls[cls];
     const RoundParams none{};
-    for (int64_t g = C.first_block + blockIdx.x; g < C.first_block + C.n_blocks; g += gridDim.x) {
-        const int c = find_chunk(T.ch, C.first_chunk, C.first_chunk + C.n_chunks - 1, g);
+    const BlockWalk W(C, schedule);
+    const int last = C.first_chunk + C.n_chunks - 1;
+    int c = W.first < W.end ? find_chunk(T.ch, C.first_chunk, last, W.first) : C.first_chunk;
+    for (int64_t g = W.first; g < W.end; g += W.step) {
+        c = next_chunk(T.ch, c, last, g, W.step);
         const BatchChunk &ch = T.ch[c];
         const int64_t local = g - ch.block_start;
         const int64_t elems = local < ch.n_full ? ch.nb : ch.last;
@@ -99,13 +140,16 @@ __global__ __launch_bounds__(64) void k_batch_encode(const uint8_t *__restrict__
 
 template <int MAXB, int EC>
 __global__ __launch_bounds__(64) void k_batch_decode(const uint8_t *__restrict__ table, int cls,
-                                                     int32_t *__restrict__ status)
+                                                     int32_t *__restrict__ status, int schedule)
 {
     __shared__ DecLds<MAXB> L;
     const TableView T(table);
     const BatchClass C = T.cls[cls];
-    for (int64_t g = C.first_block + blockIdx.x; g < C.first_block + C.n_blocks; g += gridDim.x) {
-        const int c = find_chunk(T.ch, C.first_chunk, C.first_chunk + C.n_chunks - 1, g);
+    const BlockWalk W(C, schedule);
+    const int last = C.first_chunk + C.n_chunks - 1;
+    int c = W.first < W.end ? find_chunk(T.ch, C.first_chunk, last, W.first) : C.first_chunk;
+    for (int64_t g = W.first; g < W.end; g += W.step) {
+        c = next_chunk(T.ch, c, last, g, W.step);
         const BatchChunk &ch = T.ch[c];
         const int64_t local = g - ch.block_start;
         const int64_t elems = local < ch.n_full ? ch.nb : ch.last;
@@ -256,50 +300,50 @@ int64_t persistent_grid(int64_t n_blocks, int waves_per_cu)
 }
 
 template <int MAXB, int EC>
-hipError_t launch_benc(const uint8_t *d_table, int cls, int64_t nblk, int wpc, uint8_t *slots,
-                       int32_t *sizes, hipStream_t s)
+hipError_t launch_benc(const uint8_t *d_table, int cls, int64_t nblk, int wpc, int sched,
+                       uint8_t *slots, int32_t *sizes, hipStream_t s)
 {
     hipLaunchKernelGGL((k_batch_encode<MAXB, EC>), dim3((unsigned)persistent_grid(nblk, wpc)),
-                       dim3(kWave), 0, s, d_table, cls, slots, sizes);
+                       dim3(kWave), 0, s, d_table, cls, slots, sizes, sched);
     return hipGetLastError();
 }
 
 template <int MAXB, int EC>
-hipError_t launch_bdec(const uint8_t *d_table, int cls, int64_t nblk, int wpc, int32_t *status,
-                       hipStream_t s)
+hipError_t launch_bdec(const uint8_t *d_table, int cls, int64_t nblk, int wpc, int sched,
+                       int32_t *status, hipStream_t s)
 {
     hipLaunchKernelGGL((k_batch_decode<MAXB, EC>), dim3((unsigned)persistent_grid(nblk, wpc)),
-                       dim3(kWave), 0, s, d_table, cls, status);
+                       dim3(kWave), 0, s, d_table, cls, status, sched);
     return hipGetLastError();
 }
 
 template <int MAXB>
-hipError_t benc_dispatch(int ec, const uint8_t *t, int cls, int64_t nblk, int wpc, uint8_t *slots,
-                         int32_t *sizes, hipStream_t s)
+hipError_t benc_dispatch(int ec, const uint8_t *t, int cls, int64_t nblk, int wpc, int sched,
+                         uint8_t *slots, int32_t *sizes, hipStream_t s)
 {
     switch (ec) {
-    case 1: return launch_benc<MAXB, 1>(t, cls, nblk, wpc, slots, sizes, s);
-    case 2: return launch_benc<MAXB, 2>(t, cls, nblk, wpc, slots, sizes, s);
-    case 4: return launch_benc<MAXB, 4>(t, cls, nblk, wpc, slots, sizes, s);
-    case 8: return launch_benc<MAXB, 8>(t, cls, nblk, wpc, slots, sizes, s);
-    case 12: return launch_benc<MAXB, 12>(t, cls, nblk, wpc, slots, sizes, s);
-    case 16: return launch_benc<MAXB, 16>(t, cls, nblk, wpc, slots, sizes, s);
-    default: return launch_benc<MAXB, 0>(t, cls, nblk, wpc, slots, sizes, s);
+    case 1: return launch_benc<MAXB, 1>(t, cls, nblk, wpc, sched, slots, sizes, s);
+    case 2: return launch_benc<MAXB, 2>(t, cls, nblk, wpc, sched, slots, sizes, s);
+    case 4: return launch_benc<MAXB, 4>(t, cls, nblk, wpc, sched, slots, sizes, s);
+    case 8: return launch_benc<MAXB, 8>(t, cls, nblk, wpc, sched, slots, sizes, s);
+    case 12: return launch_benc<MAXB, 12>(t, cls, nblk, wpc, sched, slots, sizes, s);
+    case 16: return launch_benc<MAXB, 16>(t, cls, nblk, wpc, sched, slots, sizes, s);
+    default: return launch_benc<MAXB, 0>(t, cls, nblk, wpc, sched, slots, sizes, s);
     }
 }
 
 template <int MAXB>
-hipError_t bdec_dispatch(int ec, const uint8_t *t, int cls, int64_t nblk, int wpc, int32_t *status,
-                         hipStream_t s)
+hipError_t bdec_dispatch(int ec, const uint8_t *t, int cls, int64_t nblk, int wpc, int sched,
+                         int32_t *status, hipStream_t s)
 {
     switch (ec) {
-    case 1: return launch_bdec<MAXB, 1>(t, cls, nblk, wpc, status, s);
-    case 2: return launch_bdec<MAXB, 2>(t, cls, nblk, wpc, status, s);
-    case 4: return launch_bdec<MAXB, 4>(t, cls, nblk, wpc, status, s);
-    case 8: return launch_bdec<MAXB, 8>(t, cls, nblk, wpc, status, s);
-    case 12: return launch_bdec<MAXB, 12>(t, cls, nblk, wpc, status, s);
-    case 16: return launch_bdec<MAXB, 16>(t, cls, nblk, wpc, status, s);
-    default: return launch_bdec<MAXB, 0>(t, cls, nblk, wpc, status, s);
+    case 1: return launch_bdec<MAXB, 1>(t, cls, nblk, wpc, sched, status, s);
+    case 2: return launch_bdec<MAXB, 2>(t, cls, nblk, wpc, sched, status, s);
+    case 4: return launch_bdec<MAXB, 4>(t, cls, nblk, wpc, sched, status, s);
+    case 8: return launch_bdec<MAXB, 8>(t, cls, nblk, wpc, sched, status, s);
+    case 12: return launch_bdec<MAXB, 12>(t, cls, nblk, wpc, sched, status, s);
+    case 16: return launch_bdec<MAXB, 16>(t, cls, nblk, wpc, sched, status, s);
+    default: return launch_bdec<MAXB, 0>(t, cls, nblk, wpc, sched, status, s);
     }
 }
 
@@ -408,9 +452,11 @@ int64_t bsg_batch_workspace_size(const void *host_table)
 }
 
 int bsg_batch_compress(const void *host_table, const void *d_table, int64_t *d_nbytes,
-                       void *workspace, int64_t workspace_bytes, int32_t waves_per_cu, void *stream)
+                       void *workspace, int64_t workspace_bytes, int32_t waves_per_cu,
+                       int32_t schedule, void *stream)
 {
     if (!host_table || !d_table || !d_nbytes || !workspace) return BSG_EINVAL;
+    if (schedule != BSG_SCHED_STRIDED && schedule != BSG_SCHED_RANGES) return BSG_EINVAL;
     if ((uintptr_t)workspace % 256 || (uintptr_t)d_table % 16 || (uintptr_t)d_nbytes % 8)
         return BSG_EINVAL;
     const TableView T(host_table);
@@ -432,8 +478,10 @@ int bsg_batch_compress(const void *host_table, const void *d_table, int64_t *d_n
     for (int c = 0; c < h.n_classes && e == hipSuccess; ++c) {
         const BatchClass &C = T.cls[c];
         if (C.n_blocks == 0) continue;
-        e = C.small ? benc_dispatch<kSmallBlock>(C.ec, t, c, C.n_blocks, waves_per_cu, slots, sizes, s)
-                    : benc_dispatch<kLargeBlock>(C.ec, t, c, C.n_blocks, waves_per_cu, slots, sizes, s);
+        e = C.small ? benc_dispatch<kSmallBlock>(C.ec, t, c, C.n_blocks, waves_per_cu, schedule,
+                                                 slots, sizes, s)
+                    : benc_dispatch<kLargeBlock>(C.ec, t, c, C.n_blocks, waves_per_cu, schedule,
+                                                 slots, sizes, s);
     }
     if (e != hipSuccess) return BSG_EHIP;
     const int64_t n_tiles = (h.total_blocks + kTile - 1) / kTile + 1; // + room for prefix[total]
@@ -451,10 +499,11 @@ int bsg_batch_compress(const void *host_table, const void *d_table, int64_t *d_n
 }
 
 int bsg_batch_decompress(const void *host_table, const void *d_table, int32_t *d_status,
-                         int32_t waves_per_cu, void *stream)
+                         int32_t waves_per_cu, int32_t schedule, void *stream)
 {
     if (!host_table || !d_table || !d_status || (uintptr_t)d_table % 16 || (uintptr_t)d_status % 4)
         return BSG_EINVAL;
+    if (schedule != BSG_SCHED_STRIDED && schedule != BSG_SCHED_RANGES) return BSG_EINVAL;
     const TableView T(host_table);
     const BatchHeader &h = *T.h;
     for (int i = 0; i < h.count; ++i)
@@ -467,8 +516,10 @@ int bsg_batch_decompress(const void *host_table, const void *d_table, int32_t *d
     for (int c = 0; c < h.n_classes && e == hipSuccess; ++c) {
         const BatchClass &C = T.cls[c];
         if (C.n_blocks == 0) continue;
-        e = C.small ? bdec_dispatch<kSmallBlock>(C.ec, t, c, C.n_blocks, waves_per_cu, d_status, s)
-                    : bdec_dispatch<kLargeBlock>(C.ec, t, c, C.n_blocks, waves_per_cu, d_status, s);
+        e = C.small ? bdec_dispatch<kSmallBlock>(C.ec, t, c, C.n_blocks, waves_per_cu, schedule,
+                                                 d_status, s)
+                    : bdec_dispatch<kLargeBlock>(C.ec, t, c, C.n_blocks, waves_per_cu, schedule,
+                                                 d_status, s);
     }
     if (e != hipSuccess) return BSG_EHIP;
     hipLaunchKernelGGL(k_batch_dec_tail, dim3((unsigned)h.count), dim3(kWave), 0, s, t, d_status);

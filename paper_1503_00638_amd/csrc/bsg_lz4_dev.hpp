@@ -778,7 +778,7 @@ __device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend,
 {
     constexpr int kBadLength = 1 << 30;
     uint8_t *b8 = reinterpret_cast<uint8_t *>(b32);
-    int ip = uni(ip0), op = 0;
+    int ip = uni(ip0);
     iend = uni(iend);
     ob = uni(ob);
     if (ip >= iend) return false; // not even a token
@@ -791,19 +791,17 @@ __device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend,
     uint32_t tok = (uint32_t)w & 255u;
     int ll, lit;
     seq_head(b8, ip, w, iend, ll, lit);
-    // literals (and so the length bytes) inside the input; output inside the
-    // block and never past unread input.  All quantities are far below 2^31:
-    // a check fails iff its difference is negative, so one sign test covers
-    // them all.
-    if (((iend - lit - ll) | (ob - ll) | lit) < 0) return false;
+    // literals (and so the length bytes) inside the input, output inside the
+    // block.  All quantities are far below 2^31: a check fails iff its
+    // difference is negative, so one sign test covers them all.
+    if (((iend - lit - ll) | (ob - ll)) < 0) return false;
     int ip2 = lit + ll;
-    int ipr = ip2 < iend ? ip2 : iend;
-    uint32_t r0 = b32[ipr >> 2], r1 = b32[(ipr >> 2) + 1];
+    uint32_t r0 = b32[ip2 >> 2], r1 = b32[(ip2 >> 2) + 1];
     dcopy(b32, 0, lit, ll);
-    op = ll;
+    int op = ll;
     while (ip2 != iend) {
         const uint64_t ow = ((uint64_t)(uint32_t)uni((int)r1) << 32 | (uint32_t)uni((int)r0)) >>
-                            (8 * (ipr & 3));
+                            (8 * (ip2 & 3));
         const int off = (int)((uint32_t)ow & 0xFFFFu);
         int ml = (int)(tok & 15u) + kMinMatch;
         int nip = ip2 + 2;
@@ -822,22 +820,21 @@ __device__ __forceinline__ bool decode_inplace(uint32_t *b32, int ip0, int iend,
                 nw = lds_le64_uni(b32, nip < iend ? nip : iend);
             }
         }
-        // offset and length bytes inside the input with a token after them
-        // (nip < iend), offset into the output so far, output inside the
-        // block and never past unread input
-        if (((iend - 1 - nip) | (off - 1) | (op - off) | (ob - op - ml) | (nip - op - ml)) < 0)
-            return false;
         // the next sequence's head (its input lies at or past nip, which the
         // match does not reach)
         const int op2 = op + ml;
         tok = (uint32_t)nw & 255u;
         int ll2, lit2;
         seq_head(b8, nip, nw, iend, ll2, lit2);
-        if (((iend - lit2 - ll2) | (ob - op2 - ll2) | (lit2 - op2)) < 0) return false;
+        // offset inside the output so far; the match ends at or before nip
+        // (output never past unread input); the next literals inside the
+        // input and the output inside the block.  These imply the rest:
+        // lit2 > nip >= op2, nip < lit2 + ll2 <= iend, op2 <= op2 + ll2 <= ob.
+        if (((off - 1) | (op - off) | (nip - op2) | (iend - lit2 - ll2) | (ob - op2 - ll2)) < 0)
+            return false;
         ip2 = lit2 + ll2;
-        ipr = ip2 < iend ? ip2 : iend;
-        r0 = b32[ipr >> 2];
-        r1 = b32[(ipr >> 2) + 1];
+        r0 = b32[ip2 >> 2];
+        r1 = b32[(ip2 >> 2) + 1];
         if (off >= ml) {
             dcopy2(b32, op, -off, op2, lit2 - op2, op2 + ll2);
         } else {

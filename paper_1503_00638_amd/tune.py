@@ -1,12 +1,20 @@
 """Launch-shape autotuner for the batch kernels.
 
-The persistent batch kernels take one knob, the resident workgroups per
-compute unit (each workgroup is one wavefront working on one block at a
-time, its block and hash table in LDS).  Fewer workgroups leave latency
-uncovered; more raise LDS and register pressure and the tail of the last
-round of blocks.  The best value depends on the mix of element classes and
-block sizes, so it is measured per batch signature and cached in a JSON
-file (``$BSG_TUNE_CACHE``, default ``~/.cache/bsg/tune.json``).
+The persistent batch kernels take two knobs, neither of which changes the
+output bytes:
+
+* waves_per_cu, the workgroups per compute unit in the grid (each workgroup
+  is one wavefront working on one block at a time, its block and hash
+  table in LDS).  Fewer leave latency uncovered; more than LDS lets reside
+  at once queue behind the first round, which balances the tail.
+* schedule, how the blocks of an element class are dealt to workgroups:
+  every grid-th block (strided) or one contiguous range per workgroup
+  (ranges), which walks the chunk table one entry at a time instead of
+  searching it per block.
+
+The best pair depends on the mix of element classes, block sizes and chunk
+sizes, so it is measured per batch signature and cached in a JSON file
+(``$BSG_TUNE_CACHE``, default ``~/.cache/bsg/tune.json``).
 """
 from __future__ import annotations
 
@@ -17,7 +25,9 @@ import statistics
 
 import torch
 
-CANDIDATES = (1, 2, 4, 8, 16, 32)
+WAVES = (4, 8, 16, 32, 64, 128)
+SCHEDULES = (0, 1)  # BSG_SCHED_STRIDED, BSG_SCHED_RANGES
+CANDIDATES = tuple((w, s) for s in SCHEDULES for w in WAVES)
 
 
 def cache_path() -> str:
@@ -77,18 +87,20 @@ def time_ms(fn, reps: int = 3, warmup: int = 1, stream=None) -> list[float]:
 
 
 def tune(plan, direction: str, candidates=CANDIDATES, reps: int = 3, use_cache: bool = True):
-    """Best waves_per_cu for plan.compress ('compress') or plan.decompress
-    ('decompress').  Returns (best, {candidate: median ms})."""
+    """Best launch shape (waves_per_cu, schedule) for plan.compress
+    ('compress') or plan.decompress ('decompress').  Returns
+    (best, {"w,s": median ms})."""
     key = signature(plan, direction)
     db = _load() if use_cache else {}
-    if use_cache and key in db:
-        return int(db[key]["best"]), {int(k): v for k, v in db[key]["ms"].items()}
+    if use_cache and key in db and isinstance(db[key].get("best"), list):
+        return tuple(db[key]["best"]), dict(db[key]["ms"])
     call = plan.compress if direction == "compress" else plan.decompress
     ms = {}
-    for w in candidates:
-        ms[w] = statistics.median(time_ms(lambda: call(waves_per_cu=w), reps=reps))
-    best = min(ms, key=ms.get)
+    for w, s in candidates:
+        ms[f"{w},{s}"] = statistics.median(
+            time_ms(lambda: call(waves_per_cu=w, schedule=s), reps=reps))
+    best = min(candidates, key=lambda c: ms[f"{c[0]},{c[1]}"])
     if use_cache:
-        db[key] = {"best": best, "ms": {str(k): v for k, v in ms.items()}}
+        db[key] = {"best": list(best), "ms": ms}
         _store(db)
     return best, ms

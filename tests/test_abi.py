@@ -128,8 +128,11 @@ def test_batch_table_host_calls(L):
     assert L.bsg_batch_build_table(bad, 1, buf, t3) == -1
     big = (_lib.Chunk * 1)(_lib.Chunk(vp(4096), 0, vp(8192), 1 << 20, 100, 8, 16384))  # 128 KiB
     assert L.bsg_batch_build_table(big, 1, buf, t3) == -1
-    assert L.bsg_batch_compress(buf, None, vp(256), vp(256), 1 << 20, 0, None) == -1
-    assert L.bsg_batch_decompress(buf, vp(17), vp(256), 0, None) == -1
+    assert L.bsg_batch_compress(buf, None, vp(256), vp(256), 1 << 20, 0, 0, None) == -1
+    assert L.bsg_batch_decompress(buf, vp(17), vp(256), 0, 0, None) == -1
+    # an unknown block schedule is refused before any device work
+    assert L.bsg_batch_compress(buf, vp(4096), vp(256), vp(256), 1 << 30, 0, 2, None) == -1
+    assert L.bsg_batch_decompress(buf, vp(4096), vp(256), 0, -1, None) == -1
 
 
 def _gfx950_kernel_metadata(lib_path, tmp_path):

@@ -89,14 +89,23 @@ def test_batch_launch_shape_does_not_change_bytes(bsg):
     xs = [to_dev(d) for d in data]
     plan = bsg.BatchPlan.for_compress(xs, Es, Bs)
     first = None
-    for w in (1, 3, 16, 64):
-        nb = host(plan.compress(waves_per_cu=w)).copy()
+    shapes = [(w, s) for s in (bsg.BSG_SCHED_STRIDED, bsg.BSG_SCHED_RANGES) for w in (1, 3, 16, 64)]
+    for w, s in shapes:
+        nb = host(plan.compress(waves_per_cu=w, schedule=s)).copy()
         got = [host(o)[: m].copy() for o, m in zip(plan.outs, nb)]
         if first is None:
             first = (nb, got)
         else:
-            assert np.array_equal(nb, first[0]), w
-            assert all(np.array_equal(a, b) for a, b in zip(got, first[1])), w
+            assert np.array_equal(nb, first[0]), (w, s)
+            assert all(np.array_equal(a, b) for a, b in zip(got, first[1])), (w, s)
+    ns = [d.size // e for d, e in zip(data, Es)]
+    dplan = bsg.BatchPlan.for_decompress(plan.outs, first[0].tolist(), ns, Es, Bs)
+    for w, s in shapes:
+        for o in dplan.outs:
+            o.fill_(0xA5)
+        assert not host(dplan.decompress(waves_per_cu=w, schedule=s)).any(), (w, s)
+        for k, d in enumerate(data):
+            assert np.array_equal(host(dplan.outs[k])[: d.size], d), (w, s, k)
 
 
 def test_batch_unaligned_chunks(bsg):

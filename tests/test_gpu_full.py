@@ -110,8 +110,10 @@ def test_batch_4096_chunks_full(bsg):
     """The batched workload at full size (4096 chunks, 64 KiB-64 MiB, about
     37 GiB) through the batch entry points in the launch shape the
     benchmark picks: every chunk decodes back to its input on the device,
-    and sampled chunks (each kind and element size, the smallest and the
-    largest) equal the oracle byte for byte, from the raw input on."""
+    and every chunk's stream equals the oracle's byte for byte, from the
+    raw input on.  The oracle side works one chunk at a time (visibility
+    chunks are regenerated from their seeds and rounded by the oracle), so
+    host memory stays bounded by the largest chunk."""
     from paper_1503_00638_amd import tune, workloads
     specs, xs = workloads.make_batch(4096, device="cuda:0")
     Es = [s.elem_size for s in specs]
@@ -119,26 +121,21 @@ def test_batch_4096_chunks_full(bsg):
     ns = [s.nbytes // s.elem_size for s in specs]
     plan = bsg.BatchPlan.for_compress(xs, Es, Bs)
     wc, _ = tune.tune(plan, "compress", use_cache=False)
-    nb = plan.compress(wc).cpu().numpy().copy()
+    nb = plan.compress(*wc).cpu().numpy().copy()
     assert (nb > 0).all()
     dplan = bsg.BatchPlan.for_decompress(plan.outs, nb.tolist(), ns, Es, Bs)
     wd, _ = tune.tune(dplan, "decompress", use_cache=False)
-    st = dplan.decompress(wd).cpu().numpy()
+    st = dplan.decompress(*wd).cpu().numpy()
     assert not st.any()
     for x, y, s in zip(xs, dplan.outs, specs):
         assert torch.equal(x, y[: s.nbytes]), s
-    by_size = sorted(range(len(specs)), key=lambda k: specs[k].nbytes)
-    picks = {by_size[0], by_size[-1]}
-    for kind in ("vis", "walk"):
-        for e in (2, 4, 8):
-            picks.add(next(k for k in range(len(specs))
-                           if specs[k].kind == kind and specs[k].elem_size == e))
-    for k in sorted(picks):
-        s = specs[k]
+    del dplan
+    checked = 0
+    for k, s in enumerate(specs):
         if s.kind == "vis":
             vis, autos = synth.gen_chunk_vis_device(s, device="cuda:0")
             r = oracle.round_to_noise(vis.cpu().numpy(), autos.cpu().numpy(), N, F_FRAC)
-            raw = r.view(np.uint8).reshape(-1)[: s.nbytes].copy()
+            raw = r.view(np.uint8).reshape(-1)[: s.nbytes]
             del vis, autos
         else:
             raw = xs[k].cpu().numpy()
@@ -146,6 +143,8 @@ def test_batch_4096_chunks_full(bsg):
         ref = oracle.compress(raw, s.elem_size, 8192 // s.elem_size)
         assert nb[k] == ref.size, s
         assert np.array_equal(plan.outs[k][: ref.size].cpu().numpy(), ref), s
+        checked += 1
+    assert checked == len(specs) == 4096
 
 
 def test_chime_chunk_byte_filter_full(bsg, chime):
