@@ -190,7 +190,7 @@ int64_t bsg_compress_workspace_size(int64_t n, int64_t elem_size, int64_t block_
 
 /* Compress n elements into the stream format above.  Every block is
  * bit-transposed and LZ4-encoded with one fixed, deterministic greedy rule
- * (hash of 4 bytes, 10 bits, Knuth's multiplier 2654435761; candidate = the
+ * (hash of 4 bytes, 9 bits, Knuth's multiplier 2654435761; candidate = the
  * last earlier position with that hash in an earlier 64-position chunk; the
  * candidate is extended forward only, keeping the last 5 bytes literal, and
  * taken when it covers at least 12 bytes starting at p <= len - 12), so the

@@ -23,7 +23,7 @@
 #define HEADER_BYTES 24
 #define DEFAULT_BLOCK_BYTES 8192
 #define MAX_BLOCK_BYTES 65536 /* LZ4 offsets are 16-bit */
-#define HASH_BITS 10
+#define HASH_BITS 9
 #define HASH_MULT 2654435761u /* Knuth's multiplicative constant */
 #define CHUNK 64             /* candidate table is updated every 64 positions */
 #define MINMATCH 4       /* LZ4 format: match lengths are coded as length - 4 */

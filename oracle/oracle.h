@@ -83,7 +83,7 @@ int oracle_bitshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_s
 int oracle_bitunshuffle(const uint8_t *in, uint8_t *out, int64_t n, int64_t elem_size,
                         int64_t block_size, int nthreads);
 
-/* One LZ4 block with the fixed greedy rule: 10-bit multiplicative hash of
+/* One LZ4 block with the fixed greedy rule: 9-bit multiplicative hash of
  * 4 bytes, candidate = the last earlier position with that hash in an
  * earlier 64-position chunk, forward extension only (the last 5 bytes stay
  * literal), a match taken when it covers at least 12 bytes and starts at

@@ -18,7 +18,7 @@ constexpr int kDefaultBlockBytes = 8192;
 
 // Fixed LZ4 match rule (a format constant: changing any of these changes the
 // compressed bytes).
-constexpr int kHashBits = 10;
+constexpr int kHashBits = 9;
 constexpr uint32_t kHashMult = 2654435761u;
 constexpr int kChunk = 64;       // the candidate table is updated per 64 positions
 constexpr int kMinMatch = 4;     // LZ4 codes match lengths as length - 4

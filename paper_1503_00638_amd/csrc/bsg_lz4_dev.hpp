@@ -933,8 +933,8 @@ __device__ __forceinline__ void copy_slot(uint8_t *__restrict__ dst, const uint8
 }
 
 // ---- one block, start to end ----------------------------------------------
-// 12 KiB for the 8 KiB block, exactly 24 of the 512-byte units LDS is
-// allocated in (13 workgroups per CU).  Reads that run past the block land
+// 10 KiB for the 8 KiB block, exactly 20 of the 512-byte units LDS is
+// allocated in (16 workgroups per CU).  Reads that run past the block land
 // in the table and are masked out.
 template <int MAXB> struct EncLds {
     uint32_t blk32[MAXB / 4];

@@ -12,7 +12,7 @@ from paper_1503_00638_amd import synth
 
 pytestmark = pytest.mark.skipif(not lz4ref.available(), reason="system liblz4 not present")
 
-HASH_BITS, CHUNK, MULT = 10, 64, 2654435761
+HASH_BITS, CHUNK, MULT = 9, 64, 2654435761
 MIN_TAKE = 12  # shortest match the rule takes
 
 
