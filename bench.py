@@ -126,6 +126,10 @@ def main(argv=None):
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-sweep", type=float, nargs="*",
+                    default=[2000.0, 5000.0, 10000.0, 20000.0, 40000.0, 80000.0],
+                    help="request rates of the serving sweep (req/s)")
+    ap.add_argument("--serve-sweep-requests", type=int, default=3000)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): blocks, chunks and "
@@ -639,7 +643,9 @@ def bench_extensions(args, torch, bsg):
 
 def bench_serve(args, torch, bsg):
     """Poisson request stream over a device-resident payload pool: the
-    continuous-batching loop against the plain per-request path."""
+    continuous-batching loop against the plain per-request path, at the
+    workload's rate (the headline) and over a sweep of rates up to
+    saturation."""
     from paper_1503_00638_amd import serve, synth, workloads
 
     dev = torch.device("cuda:0")
@@ -674,6 +680,20 @@ def bench_serve(args, torch, bsg):
             assert int(xb.item()) == 0 and int(xs.item()) == 0
             assert torch.equal(ob[: e.nbytes], e.data) and torch.equal(os_[: e.nbytes], e.data)
     sb, ss = serve.summarize(res_b, nb_b), serve.summarize(res_s, nb_s)
+    sweep = []
+    for rate in args.serve_sweep:
+        n_req = int(args.serve_sweep_requests)
+        rq = synth.gen_requests(rate, n_req / rate, sizes, seed=6)
+        row = {"rate_per_s": rate, "offered_GBps": round(sum(r.nbytes for r in rq) / (n_req / rate)
+                                                         / 1e9, 1)}
+        for mode in ("batch", "single"):
+            res, _, nb = srv.run(rq, mode)
+            sm = serve.summarize(res, nb)
+            row[mode] = {"p50_ms": sm["latency_ms"]["p50"], "p99_ms": sm["latency_ms"]["p99"],
+                         "sustained_GBps": sm["sustained_GBps"], "launches": nb}
+        sweep.append(row)
+        print(f"# rate {rate}/s: batch {row['batch']}, single {row['single']}", file=sys.stderr,
+              flush=True)
     res = {
         "metric": "uncompressed GB/s (compress & decompress) + % HBM peak; p50/p99 latency",
         "value": sb["sustained_GBps"], "unit": "GB/s", "n_gpus": 1,
@@ -684,10 +704,12 @@ def bench_serve(args, torch, bsg):
                                f"{args.serve_seconds:g} s, 60/40 decompress/compress, payloads of "
                                "noise-rounded CHIME-shaped visibilities (float32 elements, "
                                "8192-byte blocks), 256 KiB-256 MiB log-uniform, 64 GiB HBM "
-                               "budget, continuous batching on 4 streams",
+                               "budget for outputs and workspaces in flight, continuous "
+                               "batching on 4 streams",
                    "pool_payloads": len(pool), "hbm_budget": budget,
                    "parallelism": "single GPU"},
         "batched": sb, "per_request": ss,
+        "rate_sweep": {"requests_per_rate": int(args.serve_sweep_requests), "rows": sweep},
         "source_digest": source_digest(),
     }
     print(json.dumps(res), flush=True)

@@ -1,7 +1,8 @@
-"""GPU tests of the serving loop: the payload pool matches the oracle, and
+"""GPU tests of the serving loop: the payload pool matches the oracle,
 every request's result is the same served alone (the plain per-request
 path) and in the mix (continuous batching over several streams), under a
-budget that makes requests wait for memory."""
+budget that makes requests wait for memory, and the request loop makes no
+device allocation (everything comes from buffers built with the server)."""
 import numpy as np
 import pytest
 
@@ -67,6 +68,21 @@ def test_same_alone_and_in_the_mix(env, budget_mib):
         assert s.t_done >= s.t_admit >= s.t_arrival - 1e-3
     summ = serve.summarize(res_b, nb_b)
     assert summ["latency_ms"]["p99"] >= summ["latency_ms"]["p50"] > 0
+
+
+def test_request_loop_allocates_nothing(env):
+    m, serve, workloads, sizes, pool = env
+    reqs = synth.gen_requests(4000.0, 0.05, sizes, seed=23)
+    srv = serve.Server(pool, "cuda:0", hbm_budget=256 << 20, n_streams=4, max_batch=16)
+    srv.run(reqs[:10], "batch")
+    srv.run(reqs[:10], "single")
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_stats()["allocation.all.allocated"]
+    _, _, nb_b = srv.run(reqs, "batch")
+    _, _, nb_s = srv.run(reqs, "single")
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_stats()["allocation.all.allocated"] == before
+    assert nb_s == len(reqs) and nb_b < len(reqs)
 
 
 def test_request_over_budget_is_refused(env):
