@@ -430,8 +430,9 @@ def _lz4_len(n):
 
 def test_decode_rejects_overlong_literals(bsg):
     """Blocks whose literal runs end past the block (as the last sequence,
-    or before a match) and a block with no bytes at all are rejected, as by
-    the oracle, and the blocks around them still decode."""
+    or before a match), whose match offset is 0 or reaches before the
+    block's start, and a block with no bytes at all are rejected, as by the
+    oracle, and the blocks around them still decode."""
     E, nb = 4, 2048
     n = nb * E
     rng = np.random.default_rng(23)
@@ -450,6 +451,9 @@ def test_decode_rejects_overlong_literals(bsg):
         seq(n - 2, lit, off=1, ml=10) + seq(0, b""),      # match past the block
         seq(n + 3, lit, off=1, ml=4) + seq(0, b""),       # literals past it, then a match
         b"",                                              # no token at all
+        seq(8, lit, off=0, ml=4) + seq(0, b""),           # offset 0
+        seq(8, lit, off=9, ml=4) + seq(0, b""),           # offset before the block start
+        seq(8, lit, off=8, ml=n - 10) + seq(5, lit),      # next literals end past the block
     ]
     for bad in bad_blocks:
         with pytest.raises(oracle.OracleError):
