@@ -238,8 +238,9 @@ def main(argv=None):
     bytes_dec = m + U
     if comp >= dcm:
         dominant, dom_ms, dom_bytes, tkey = (
-            "round_compress call: k_encode<8192,4,true> + k_tile_sum + k_tile_offsets + "
-            "k_write_offsets + k_pack", comp, bytes_comp, "round_compress_call")
+            "round_compress call: k_encode<8192,4,1> in 16 segments on two streams, "
+            "k_tile_sum + k_tile_offsets + k_write_offsets + k_pack per segment on a third",
+            comp, bytes_comp, "round_compress_call")
     else:
         dominant, dom_ms, dom_bytes, tkey = ("decompress call: k_decode<8192,4>", dcm, bytes_dec,
                                              "decompress_call")

@@ -19,8 +19,11 @@
  *    (BSG_OK or a negative BSG_E* code).  Results that depend on the data
  *    (compressed size, decode status) are written to caller-provided device
  *    words.
- *  - No global mutable state: calls on different streams may run concurrently
- *    (the paper's thread-safety requirement, Section 2 and Section 4.2).
+ *  - Calls on different streams may run concurrently (the paper's
+ *    thread-safety requirement, Section 2 and Section 4.2).  The only state
+ *    the library keeps is made once per device and guarded by locks: the
+ *    two streams and their events of the segmented compression
+ *    (bsg_compress_lz4) and the scratch array of bsg_compress_lz4_noalloc.
  *  - block_size is counted in ELEMENTS and must be a multiple of 8; 0 selects
  *    the default, 8192 bytes' worth of elements rounded down to a multiple of 8.
  *    A block of n_B elements is transposed as an (n_B x 8E) bit matrix.  The
@@ -202,7 +205,13 @@ int64_t bsg_compress_workspace_size(int64_t n, int64_t elem_size, int64_t block_
  *   to never see that.
  * workspace: device memory of bsg_compress_workspace_size bytes, 256-byte
  *   aligned; workspace_bytes is its size.  Blocks above 65536 bytes are
- *   rejected (BSG_EINVAL). */
+ *   rejected (BSG_EINVAL).
+ * stream: an input of 16384 blocks or more is encoded in up to 16 segments
+ *   on this stream and one of the library's own, while a third stream (also
+ *   the library's: both made once per device, default priority) copies each
+ *   finished segment's blocks to their place; both are joined back into
+ *   this stream, so the call orders like one operation on it, also under
+ *   stream capture.  Host threads enqueueing such calls take turns. */
 int bsg_compress_lz4(const void *in, void *out, int64_t n, int64_t elem_size,
                      int64_t block_size, int64_t out_capacity, int64_t *d_out_nbytes,
                      void *workspace, int64_t workspace_bytes, void *stream);
@@ -212,7 +221,8 @@ int bsg_compress_lz4(const void *in, void *out, int64_t n, int64_t elem_size,
  * hipMalloc): no workspace argument; the scratch space (block slots, block
  * sizes, scan tiles) is a fixed array of BSG_NOALLOC_SCRATCH_BYTES inside the
  * library, one per GPU, held from the library's load until the process
- * ends.  The call allocates nothing.  It uses the device current on the
+ * ends.  The call allocates nothing (it never uses the library's own
+ * streams: a large input is encoded in one pass on `stream`).  It uses the device current on the
  * calling thread (the stream must belong to it).  Same stream format, bytes,
  * bounds and errors as bsg_compress_lz4, plus BSG_ECAPACITY when
  * bsg_compress_workspace_size(n, elem_size, block_size) exceeds

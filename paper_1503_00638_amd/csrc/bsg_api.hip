@@ -273,7 +273,8 @@ int64_t bsg_compress_workspace_size(int64_t n, int64_t elem_size, int64_t block_
 
 static int compress_common(const void *in, void *out, const Layout &L, int64_t out_capacity,
                            int64_t *d_out_nbytes, void *workspace, int64_t workspace_bytes,
-                           const RoundParams *rp, void *stream, int filter = BSG_FILTER_BIT)
+                           const RoundParams *rp, void *stream, int filter = BSG_FILTER_BIT,
+                           bool may_segment = true)
 {
     if (filter != BSG_FILTER_BIT && filter != BSG_FILTER_BYTE) return BSG_EINVAL;
     if (L.block_bytes() > BSG_MAX_BLOCK_BYTES) return BSG_EINVAL;
@@ -284,7 +285,7 @@ static int compress_common(const void *in, void *out, const Layout &L, int64_t o
     if (out_capacity < fixed_stream_bytes(L)) return BSG_ECAPACITY;
     return hip_status(launch_compress(static_cast<const uint8_t *>(in), static_cast<uint8_t *>(out),
                                       L, out_capacity, d_out_nbytes, workspace, workspace_bytes, rp,
-                                      static_cast<hipStream_t>(stream), filter));
+                                      static_cast<hipStream_t>(stream), filter, may_segment));
 }
 
 int bsg_compress_lz4(const void *in, void *out, int64_t n, int64_t elem_size, int64_t block_size,
@@ -312,7 +313,8 @@ int bsg_compress_lz4_noalloc(const void *in, void *out, int64_t n, int64_t elem_
     const int st = scratch_for_current_device(&ws);
     if (st != BSG_OK) return st;
     return compress_common(in, out, L, out_capacity, d_out_nbytes, ws,
-                           (int64_t)BSG_NOALLOC_SCRATCH_BYTES, nullptr, stream);
+                           (int64_t)BSG_NOALLOC_SCRATCH_BYTES, nullptr, stream, BSG_FILTER_BIT,
+                           false);
 }
 
 int bsg_compress_lz4_filter(const void *in, void *out, int64_t n, int64_t elem_size,

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(64) void k_batch_encode(const uint8_t *__restrict__
         const BatchChunk &ch = T.ch[c];
         const int64_t local = g - ch.block_start;
         const int64_t elems = local < ch.n_full ? ch.nb : ch.last;
-        const int sz = encode_one<MAXB, EC, false>(ch.in + local * ch.nb * ch.E, elems, ch.E, none, 0,
+        const int sz = encode_one<MAXB, EC, kRoundNone>(ch.in + local * ch.nb * ch.E, elems, ch.E, none, 0,
                                                    slots + ch.slot_start + local * ch.slot_bytes, L);
         if (threadIdx.x == 0) sizes[g] = sz;
     }

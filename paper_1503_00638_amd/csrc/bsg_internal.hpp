@@ -175,9 +175,12 @@ hipError_t launch_shuffle(const uint8_t *in, uint8_t *out, const Layout &L, bool
                           hipStream_t s);
 hipError_t launch_byteshuffle(const uint8_t *in, uint8_t *out, const Layout &L, bool inverse,
                               hipStream_t s);
+// may_segment: a large input may be encoded in segments over the library's
+// own streams (off for callers that must not create anything).
 hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int64_t cap,
                            int64_t *d_nbytes, void *ws, int64_t ws_bytes,
-                           const RoundParams *rp, hipStream_t s, int filter = BSG_FILTER_BIT);
+                           const RoundParams *rp, hipStream_t s, int filter = BSG_FILTER_BIT,
+                           bool may_segment = true);
 int64_t compress_workspace(const Layout &L);
 hipError_t launch_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out,
                              const Layout &L, int32_t *d_status, hipStream_t s, int filter = BSG_FILTER_BIT);

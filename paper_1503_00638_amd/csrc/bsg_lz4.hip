@@ -6,9 +6,15 @@
 // Compression = k_encode (transpose into LDS [+ fused rounding], LDS hash
 // table, greedy parse, write to a bound-sized slot) -> k_tile_sum ->
 // k_tile_offsets (one workgroup) -> k_write_offsets -> k_pack (copy slots to
-// their final place, header, raw tail).
+// their final place, header, raw tail).  A large input is encoded in
+// segments on two streams while a third stream scans and packs each
+// finished segment, so the copy out of the slots runs under the encoding
+// of the next segments (the encoder is bound by instruction issue, the
+// copy by HBM).
 // Decompression = k_decode (stage the LZ4 block in LDS, decode into LDS,
 // inverse transpose on the way out to HBM).
+#include <mutex>
+
 #include "bsg_lz4_dev.hpp"
 
 namespace bsg {
@@ -24,49 +30,56 @@ struct EncArgs {
     int64_t block0; // index of the first block of this launch
 };
 
-template <int MAXB, int EC, bool ROUND>
+template <int MAXB, int EC, int RM>
 __global__ __launch_bounds__(64) void k_encode(EncArgs a, RoundParams rp)
 {
     __shared__ EncLds<MAXB> L;
     const int64_t b = a.block0 + blockIdx.x;
     const int64_t elems = b < a.n_full ? a.nb : a.last;
     const int64_t first = b * a.nb;
-    const int sz = encode_one<MAXB, EC, ROUND>(a.in + first * a.E, elems, a.E, rp, first,
+    const int sz = encode_one<MAXB, EC, RM>(a.in + first * a.E, elems, a.E, rp, first,
                                                a.slots + b * a.slot_bytes, L);
     if (threadIdx.x == 0) a.sizes[b] = sz;
 }
 
 // tile_sum[k] = sum of sizes over blocks [k * kTile, (k + 1) * kTile)
 __global__ __launch_bounds__(256) void k_tile_sum(const int32_t *__restrict__ sizes,
-                                                  int64_t n_blocks, int64_t *__restrict__ tile_sum)
+                                                  int64_t n_blocks, int64_t tile0,
+                                                  int64_t *__restrict__ tile_sum)
 {
     __shared__ int64_t sh[256];
-    const int64_t base = int64_t(blockIdx.x) * kTile;
+    const int64_t tile = tile0 + blockIdx.x;
+    const int64_t base = tile * kTile;
     int64_t s = 0;
     for (int k = threadIdx.x; k < kTile; k += 256)
         if (base + k < n_blocks) s += sizes[base + k];
     const int64_t inc = block_sum_i64(s, sh);
-    if (threadIdx.x == 255) tile_sum[blockIdx.x] = inc;
+    if (threadIdx.x == 255) tile_sum[tile] = inc;
 }
 
-// One workgroup: exclusive scan of the tile sums (in place), stream total,
-// capacity verdict, stream header.
+// One workgroup: exclusive scan of the tile sums of tiles [t0, t1) (in
+// place) after the payload bytes of the tiles before t0 (*carry, 0 when t0 =
+// 0); leaves the payload bytes up to t1 in *carry.  With last set: stream
+// total, capacity verdict, stream header.
 __global__ __launch_bounds__(256) void k_tile_offsets(int64_t *__restrict__ tile_sum,
-                                                      int64_t n_tiles, int64_t fixed_bytes,
-                                                      int64_t cap, int64_t *__restrict__ d_nbytes,
+                                                      int64_t t0, int64_t t1,
+                                                      int64_t *__restrict__ carry_io, int last,
+                                                      int64_t fixed_bytes, int64_t cap,
+                                                      int64_t *__restrict__ d_nbytes,
                                                       uint8_t *__restrict__ out, bsg_header hdr)
 {
     __shared__ int64_t sh[256];
-    int64_t carry = 0;
-    for (int64_t base = 0; base < n_tiles; base += 256) {
+    int64_t carry = t0 > 0 ? *carry_io : 0;
+    for (int64_t base = t0; base < t1; base += 256) {
         const int64_t k = base + threadIdx.x;
-        const int64_t v = k < n_tiles ? tile_sum[k] : 0;
+        const int64_t v = k < t1 ? tile_sum[k] : 0;
         const int64_t inc = block_sum_i64(v, sh);
-        if (k < n_tiles) tile_sum[k] = carry + inc - v;
+        if (k < t1) tile_sum[k] = carry + inc - v;
         carry += sh[255];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !last) *carry_io = carry;
+    if (threadIdx.x == 0 && last) {
         const int64_t total = fixed_bytes + carry;
         *d_nbytes = total <= cap ? total : (int64_t)BSG_ECAPACITY;
         *reinterpret_cast<bsg_header *>(out) = hdr;
@@ -77,13 +90,14 @@ __global__ __launch_bounds__(256) void k_tile_offsets(int64_t *__restrict__ tile
 
 // off[b] for every block of a tile (written straight into the stream).
 __global__ __launch_bounds__(256) void k_write_offsets(const int32_t *__restrict__ sizes,
-                                                       int64_t n_blocks,
+                                                       int64_t n_blocks, int64_t tile0,
                                                        const int64_t *__restrict__ tile_off,
                                                        uint8_t *__restrict__ out)
 {
     __shared__ int64_t sh[256];
     constexpr int PER = kTile / 256;
-    const int64_t base = int64_t(blockIdx.x) * kTile + threadIdx.x * PER;
+    const int64_t tile = tile0 + blockIdx.x;
+    const int64_t base = tile * kTile + threadIdx.x * PER;
     int64_t v[PER];
     int64_t s = 0;
 #pragma unroll
@@ -92,7 +106,7 @@ __global__ __launch_bounds__(256) void k_write_offsets(const int32_t *__restrict
         s += v[k];
     }
     const int64_t inc = block_sum_i64(s, sh);
-    int64_t o = tile_off[blockIdx.x] + inc - s;
+    int64_t o = tile_off[tile] + inc - s;
     uint64_t *off = reinterpret_cast<uint64_t *>(out + kHeaderBytes);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -101,27 +115,27 @@ __global__ __launch_bounds__(256) void k_write_offsets(const int32_t *__restrict
     }
 }
 
-// Copy each block's LZ4 bytes from its slot to the payload; the extra last
-// workgroup copies the raw tail.  Nothing is written when the stream does
-// not fit (d_nbytes < 0).
+// Copy the LZ4 bytes of blocks block0, block0 + 1, ... from their slots to
+// the payload; block n_blocks (in the last launch) stands for the raw tail.
+// Nothing is written past the output's capacity: a block whose bytes would
+// end past payload_cap is skipped (the stream then does not fit and the
+// call reports so), and the tail is written only when the stream fits
+// (d_nbytes >= 0, known by the time the last launch runs).
 __global__ __launch_bounds__(64) void k_pack(const uint8_t *__restrict__ slots, int64_t slot_bytes,
                                              const int32_t *__restrict__ sizes, int64_t n_blocks,
+                                             int64_t block0, int64_t payload_cap,
                                              uint8_t *__restrict__ out,
                                              const int64_t *__restrict__ d_nbytes,
                                              const uint8_t *__restrict__ tail_src,
                                              int64_t tail_bytes, RoundParams rp, int round_tail,
                                              int64_t tail_first_elem)
 {
-    const int64_t b = blockIdx.x;
+    const int64_t b = block0 + blockIdx.x;
     const uint64_t *off = reinterpret_cast<const uint64_t *>(out + kHeaderBytes);
-    // (the three loads issue together)
-    const int64_t nbytes = *d_nbytes;
-    const uint64_t ob = off[b];
-    const int sz = b < n_blocks ? sizes[b] : 0;
-    if (nbytes < 0) return;
     uint8_t *payload = out + kHeaderBytes + 8 * (n_blocks + 1);
     const int lane = threadIdx.x;
     if (b == n_blocks) {
+        if (*d_nbytes < 0) return;
         uint8_t *dst = payload + off[n_blocks];
         if (round_tail) { // the raw tail of the fused path is rounded too (float32 elements)
             for (int64_t k = lane; k < tail_bytes / 4; k += kWave) {
@@ -135,6 +149,9 @@ __global__ __launch_bounds__(64) void k_pack(const uint8_t *__restrict__ slots, 
         for (int64_t i = lane; i < tail_bytes; i += kWave) dst[i] = tail_src[i];
         return;
     }
+    const uint64_t ob = off[b];
+    const int sz = sizes[b];
+    if ((int64_t)(ob + sz) > payload_cap) return;
     copy_slot(payload + ob, slots + b * slot_bytes, sz);
 }
 
@@ -174,12 +191,12 @@ __global__ __launch_bounds__(64) void k_decode(DecArgs a)
         fail(a.status);
 }
 
-template <int MAXB, int EC, bool ROUND>
+template <int MAXB, int EC, int RM>
 hipError_t encode_launch(const EncArgs &ea, int64_t nblocks, const RoundParams &rp,
                          hipStream_t s)
 {
     if (nblocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_encode<MAXB, EC, ROUND>), dim3((unsigned)nblocks), dim3(kWave), 0, s, ea,
+    hipLaunchKernelGGL((k_encode<MAXB, EC, RM>), dim3((unsigned)nblocks), dim3(kWave), 0, s, ea,
                        rp);
     return hipGetLastError();
 }
@@ -189,17 +206,20 @@ hipError_t encode_dispatch(const EncArgs &ea, int64_t nblocks, const RoundParams
                            hipStream_t s)
 {
     const RoundParams none{};
-    if (rp) return ec == 4 ? encode_launch<MAXB, 4, true>(ea, nblocks, *rp, s)
-                           : encode_launch<MAXB, 0, true>(ea, nblocks, *rp, s);
+    if (rp) {
+        if (ec != 4) return encode_launch<MAXB, 0, kRoundPlain>(ea, nblocks, *rp, s);
+        return rp->fscale ? encode_launch<MAXB, 4, kRoundScaled>(ea, nblocks, *rp, s)
+                          : encode_launch<MAXB, 4, kRoundPlain>(ea, nblocks, *rp, s);
+    }
     switch (ec) {
-    case kByteShuffle: return encode_launch<MAXB, kByteShuffle, false>(ea, nblocks, none, s);
-    case 1: return encode_launch<MAXB, 1, false>(ea, nblocks, none, s);
-    case 2: return encode_launch<MAXB, 2, false>(ea, nblocks, none, s);
-    case 4: return encode_launch<MAXB, 4, false>(ea, nblocks, none, s);
-    case 8: return encode_launch<MAXB, 8, false>(ea, nblocks, none, s);
-    case 12: return encode_launch<MAXB, 12, false>(ea, nblocks, none, s);
-    case 16: return encode_launch<MAXB, 16, false>(ea, nblocks, none, s);
-    default: return encode_launch<MAXB, 0, false>(ea, nblocks, none, s);
+    case kByteShuffle: return encode_launch<MAXB, kByteShuffle, kRoundNone>(ea, nblocks, none, s);
+    case 1: return encode_launch<MAXB, 1, kRoundNone>(ea, nblocks, none, s);
+    case 2: return encode_launch<MAXB, 2, kRoundNone>(ea, nblocks, none, s);
+    case 4: return encode_launch<MAXB, 4, kRoundNone>(ea, nblocks, none, s);
+    case 8: return encode_launch<MAXB, 8, kRoundNone>(ea, nblocks, none, s);
+    case 12: return encode_launch<MAXB, 12, kRoundNone>(ea, nblocks, none, s);
+    case 16: return encode_launch<MAXB, 16, kRoundNone>(ea, nblocks, none, s);
+    default: return encode_launch<MAXB, 0, kRoundNone>(ea, nblocks, none, s);
     }
 }
 
@@ -234,12 +254,45 @@ int64_t compress_workspace(const Layout &L)
     int64_t ws = L.n_blocks * slot;
     ws = (ws + 255) / 256 * 256 + ((L.n_blocks * 4 + 255) / 256) * 256;
     ws += ((n_tiles * 8 + 255) / 256) * 256;
-    return ws > 0 ? ws : 256;
+    ws += 256; // the payload bytes carried from one segment to the next
+    return ws;
+}
+
+// Streams and events of one device for the segmented compression, made
+// once (default priority).  Guarded by seg_mu, which is held while a call
+// enqueues its work, so calls from several host threads do not interleave
+// their use of the shared events.
+constexpr int kMaxSeg = 16;                // segments of a large input
+constexpr int64_t kSegMinBlocks = 8192;    // ... of at least this many blocks
+struct SegStreams {
+    bool made = false, ok = false;
+    hipStream_t enc = nullptr, pack = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, done[kMaxSeg] = {};
+};
+constexpr int kMaxSegDevices = 64;
+std::mutex seg_mu;
+SegStreams seg_dev[kMaxSegDevices]; // guarded by seg_mu
+
+SegStreams *seg_streams_locked(int dev)
+{
+    if (dev < 0 || dev >= kMaxSegDevices) return nullptr;
+    SegStreams &g = seg_dev[dev];
+    if (!g.made) {
+        g.made = true;
+        bool ok = hipStreamCreateWithFlags(&g.enc, hipStreamNonBlocking) == hipSuccess &&
+                  hipStreamCreateWithFlags(&g.pack, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&g.fork, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&g.join, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; ok && i < kMaxSeg; ++i)
+            ok = hipEventCreateWithFlags(&g.done[i], hipEventDisableTiming) == hipSuccess;
+        g.ok = ok;
+    }
+    return g.ok ? &g : nullptr;
 }
 
 hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int64_t cap,
                            int64_t *d_nbytes, void *ws, int64_t ws_bytes, const RoundParams *rp,
-                           hipStream_t s, int filter)
+                           hipStream_t s, int filter, bool may_segment)
 {
     (void)ws_bytes;
     const int64_t slot = (lz4_bound(L.block_bytes()) + 15) / 16 * 16;
@@ -250,35 +303,75 @@ hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int
     int32_t *sizes = reinterpret_cast<int32_t *>(w + pos);
     pos += ((L.n_blocks * 4 + 255) / 256) * 256;
     int64_t *tile_sum = reinterpret_cast<int64_t *>(w + pos);
+    pos += ((n_tiles * 8 + 255) / 256) * 256;
+    int64_t *carry = reinterpret_cast<int64_t *>(w + pos);
 
-    EncArgs ea{in, L.nb, L.E, L.n_full, L.last, slots, slot, sizes, 0};
     RoundParams none{};
     const int ec = filter == BSG_FILTER_BYTE ? kByteShuffle : element_class(L.E);
-    hipError_t e = L.block_bytes() <= kSmallBlock
-                       ? encode_dispatch<kSmallBlock>(ea, L.n_blocks, rp, ec, s)
-                       : encode_dispatch<kLargeBlock>(ea, L.n_blocks, rp, ec, s);
-    if (e != hipSuccess) return e;
-
-    bsg_header hdr{filter == BSG_FILTER_BYTE ? BSG_MAGIC_BYTE : BSG_MAGIC, (uint32_t)L.E, (uint64_t)L.n, (uint32_t)L.nb, (uint32_t)L.n_blocks};
+    bsg_header hdr{filter == BSG_FILTER_BYTE ? BSG_MAGIC_BYTE : BSG_MAGIC, (uint32_t)L.E,
+                   (uint64_t)L.n, (uint32_t)L.nb, (uint32_t)L.n_blocks};
     const int64_t fixed = kHeaderBytes + 8 * (L.n_blocks + 1) + L.tail * L.E;
-    if (n_tiles > 0) {
-        hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)n_tiles), dim3(256), 0, s, sizes, L.n_blocks,
-                           tile_sum);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(256), 0, s, tile_sum, n_tiles, fixed, cap,
-                       d_nbytes, out, hdr);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (n_tiles > 0) {
-        hipLaunchKernelGGL(k_write_offsets, dim3((unsigned)n_tiles), dim3(256), 0, s, sizes,
-                           L.n_blocks, tile_sum, out);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
     const uint8_t *tail_src = in + (L.n - L.tail) * L.E;
-    hipLaunchKernelGGL(k_pack, dim3((unsigned)(L.n_blocks + 1)), dim3(kWave), 0, s, slots, slot,
-                       sizes, L.n_blocks, out, d_nbytes, tail_src, L.tail * L.E,
-                       rp ? *rp : none, rp ? 1 : 0, L.n - L.tail);
-    return hipGetLastError();
+
+    // segments of whole tiles
+    int nseg = (int)std::min<int64_t>(kMaxSeg, L.n_blocks / kSegMinBlocks);
+    if (nseg < 1 || !may_segment) nseg = 1;
+    std::unique_lock<std::mutex> lock(seg_mu, std::defer_lock);
+    SegStreams *g = nullptr;
+    hipError_t e;
+    if (nseg > 1) {
+        int dev = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+        lock.lock();
+        g = seg_streams_locked(dev);
+        if (!g) return hipErrorOutOfMemory;
+        if ((e = hipEventRecord(g->fork, s)) != hipSuccess ||
+            (e = hipStreamWaitEvent(g->enc, g->fork, 0)) != hipSuccess ||
+            (e = hipStreamWaitEvent(g->pack, g->fork, 0)) != hipSuccess)
+            return e;
+    }
+    hipStream_t ps = g ? g->pack : s;
+    for (int i = 0; i < nseg; ++i) {
+        const int64_t t0 = n_tiles * i / nseg, t1 = n_tiles * (i + 1) / nseg;
+        const int64_t b0 = t0 * kTile, b1 = std::min(t1 * kTile, L.n_blocks);
+        const bool last = i == nseg - 1;
+        hipStream_t es = (g && (i & 1)) ? g->enc : s;
+        EncArgs ea{in, L.nb, L.E, L.n_full, L.last, slots, slot, sizes, b0};
+        e = L.block_bytes() <= kSmallBlock ? encode_dispatch<kSmallBlock>(ea, b1 - b0, rp, ec, es)
+                                           : encode_dispatch<kLargeBlock>(ea, b1 - b0, rp, ec, es);
+        if (e != hipSuccess) return e;
+        if (g && ((e = hipEventRecord(g->done[i], es)) != hipSuccess ||
+                  (e = hipStreamWaitEvent(ps, g->done[i], 0)) != hipSuccess))
+            return e;
+        if (t1 > t0) {
+            hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)(t1 - t0)), dim3(256), 0, ps, sizes,
+                               L.n_blocks, t0, tile_sum);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_tile_offsets, dim3(1), dim3(256), 0, ps, tile_sum, t0, t1, carry,
+                           last ? 1 : 0, fixed, cap, d_nbytes, out, hdr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (t1 > t0) {
+            hipLaunchKernelGGL(k_write_offsets, dim3((unsigned)(t1 - t0)), dim3(256), 0, ps,
+                               sizes, L.n_blocks, t0, tile_sum, out);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        const int64_t npack = b1 - b0 + (last ? 1 : 0);
+        if (npack > 0) {
+            hipLaunchKernelGGL(k_pack, dim3((unsigned)npack), dim3(kWave), 0, ps, slots, slot,
+                               sizes, L.n_blocks, b0, cap - fixed, out, d_nbytes, tail_src,
+                               L.tail * L.E, rp ? *rp : none, rp ? 1 : 0, L.n - L.tail);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    // join both internal streams back into the caller's (the encode stream
+    // also directly, so that a stream capture sees it joined)
+    if (g && ((e = hipEventRecord(g->join, ps)) != hipSuccess ||
+              (e = hipStreamWaitEvent(s, g->join, 0)) != hipSuccess ||
+              (e = hipStreamWaitEvent(s, g->done[(nseg & 1) ? nseg - 2 : nseg - 1], 0)) !=
+                  hipSuccess))
+        return e;
+    return hipSuccess;
 }
 
 hipError_t launch_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out, const Layout &L,

@@ -26,6 +26,15 @@ typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
 // accesses of one wave complete in order, but no access moves across it).  A
 // workgroup barrier would also wait for every outstanding global load and
 // store of the wave.
+// The lane index, opaque to the optimiser, for the encoder: values derived
+// from it are then not hoisted out of the persistent block loop, where they
+// would stay live across the whole loop body and cost occupancy.
+__device__ __forceinline__ int lane_id()
+{
+    int x = (int)threadIdx.x;
+    asm volatile("" : "+v"(x));
+    return x;
+}
 __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
 constexpr int kDppWaveShl1 = 0x130;
@@ -39,17 +48,22 @@ __device__ __forceinline__ uint32_t lds_le32(const uint32_t *b32, int pos)
 }
 
 // ---- stage the block into LDS as bit planes -------------------------------
-template <int E, bool ROUND>
+// Stage-1 rounding fused into the encoder's staging: none, plain, or with a
+// per-(frequency, time) factor on the variance (separate instances, as the
+// factors' registers would lower the occupancy of the plain one).
+constexpr int kRoundNone = 0, kRoundPlain = 1, kRoundScaled = 2;
+
+template <int E, int RM>
 __device__ __forceinline__ void stage_fast(const uint8_t *__restrict__ src, int64_t elems,
                                            uint8_t *lds, const RoundParams &rp,
                                            int64_t first_elem)
 {
-    const int lane = threadIdx.x;
+    const int lane = lane_id();
     const int64_t units = elems / Unit<E>::G;
     for (int64_t u = lane; u < units; u += kWave) {
         uint32_t w[Unit<E>::IN_WORDS];
         load_unit<E>(src + u * (Unit<E>::G * E), w);
-        if constexpr (ROUND) {
+        if constexpr (RM != kRoundNone) {
             // E == 4: the unit is 32 float32 = 16 complex64 visibilities.
             VisCursor c = cursor_at(rp, (first_elem + u * 32) / 2);
             if (c.t + 16 <= rp.T) {
@@ -59,14 +73,13 @@ __device__ __forceinline__ void stage_fast(const uint8_t *__restrict__ src, int6
                 const float *pj = rp.autos + c.row_j + c.t;
                 const bool is_auto = c.i == c.j;
                 float ai[16], aj[16];
-                double sc[16];
+                double sc[RM == kRoundScaled ? 16 : 1];
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     ai[k] = pi[k];
                     aj[k] = pj[k];
-                    sc[k] = 1.0;
                 }
-                if (rp.fscale) {
+                if constexpr (RM == kRoundScaled) {
                     const double *fs = rp.fscale + c.fr * rp.T + c.t;
 #pragma unroll
                     for (int k = 0; k < 16; ++k) sc[k] = fs[k];
@@ -74,7 +87,7 @@ __device__ __forceinline__ void stage_fast(const uint8_t *__restrict__ src, int6
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     double G2 = ((double)ai[k] * (double)aj[k]) * (is_auto ? rp.c_auto : rp.c);
-                    if (rp.fscale) G2 *= sc[k];
+                    if constexpr (RM == kRoundScaled) G2 *= sc[k];
                     w[2 * k] = round_noise_bits_nb(w[2 * k], G2);
                     if (!is_auto) w[2 * k + 1] = round_noise_bits_nb(w[2 * k + 1], G2);
                 }
@@ -103,7 +116,7 @@ __device__ __forceinline__ void block_forward_ballot_round(const uint8_t *__rest
                                                            const RoundParams &rp,
                                                            int64_t first_elem)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_id();
     const int64_t pb = elems / 8;
     for (int64_t g = 0; g < elems; g += 64) {
         const int64_t i = g + lane;
@@ -134,7 +147,7 @@ __device__ __forceinline__ void block_forward_bytes(const uint8_t *__restrict__ 
                                                     int64_t elems, int64_t E)
 {
     uint32_t *l32 = reinterpret_cast<uint32_t *>(lds);
-    for (int64_t g = threadIdx.x; g < elems / 4; g += kWave) {
+    for (int64_t g = lane_id(); g < elems / 4; g += kWave) {
         const uint8_t *src = in + 4 * g * E;
         for (int64_t k = 0; k < E; ++k)
             l32[(k * elems + 4 * g) >> 2] = (uint32_t)src[k] | ((uint32_t)src[E + k] << 8) |
@@ -161,15 +174,15 @@ __device__ __forceinline__ void block_inverse_bytes(const uint8_t *lds, uint8_t 
 
 // EC: the element size this kernel instance has a register fast path for
 // (1, 2, 4, 8, 12, 16), 0 for the generic ballot path only, or kByteShuffle.
-template <int EC, bool ROUND>
+template <int EC, int RM>
 __device__ __forceinline__ void stage_block(const uint8_t *__restrict__ src, int64_t elems,
                                             int64_t E, uint8_t *lds, const RoundParams &rp,
                                             int64_t first_elem)
 {
-    if constexpr (ROUND) {
+    if constexpr (RM != kRoundNone) {
         static_assert(EC == 4 || EC == 0, "rounding is fused for float32 elements only");
         if (EC == 4 && elems % 32 == 0 && ((uintptr_t)src % 16) == 0)
-            stage_fast<4, true>(src, elems, lds, rp, first_elem);
+            stage_fast<4, RM>(src, elems, lds, rp, first_elem);
         else
             block_forward_ballot_round(src, lds, elems, rp, first_elem);
     } else if constexpr (EC == kByteShuffle) {
@@ -177,7 +190,7 @@ __device__ __forceinline__ void stage_block(const uint8_t *__restrict__ src, int
     } else {
         if constexpr (EC != 0) {
             if (elems % Unit<EC>::G == 0 && ((uintptr_t)src % 16) == 0) {
-                stage_fast<EC, false>(src, elems, lds, rp, first_elem);
+                stage_fast<EC, kRoundNone>(src, elems, lds, rp, first_elem);
                 return;
             }
         }
@@ -222,7 +235,7 @@ __device__ __forceinline__ uint32_t lds_le32_head(const uint32_t *b32, int pos)
 __device__ __forceinline__ int emit_sequences(uint8_t *__restrict__ dst, int op, const uint32_t *b32,
                                               int ns, int lit, int ll, int off, int ml)
 {
-    const int lane = threadIdx.x;
+    const int lane = lane_id();
     const bool act = lane < ns;
     const bool last = ml == 0;
     const int mlc = last ? 0 : ml - kMinMatch;
@@ -303,7 +316,7 @@ __device__ __forceinline__ int emit_sequences(uint8_t *__restrict__ dst, int op,
 template <int MAXB>
 __device__ __forceinline__ int extend_match(const uint32_t *b32, int c, int q, int L, int maxL)
 {
-    const int lane = threadIdx.x;
+    const int lane = lane_id();
     if (L >= maxL) return maxL;
     if (L + 4 * kWave <= maxL) {
         // the whole first step lies inside the block and the limit
@@ -372,7 +385,7 @@ __device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table,
                                            int last_ins, u32x16 &candv)
 {
     constexpr int NC = kGroup / kChunk;
-    const int lane = threadIdx.x;
+    const int lane = lane_id();
     uint32_t vv[NC];
     const uint32_t *dg = b32 + ((g0 + lane) >> 2);
 #pragma unroll
@@ -432,7 +445,7 @@ __device__ __forceinline__ void hash_group(const uint32_t *b32, uint32_t *table,
 __device__ __forceinline__ uint64_t verify_chunk(const uint32_t *b32, int c0, uint32_t cand,
                                                  int last_take)
 {
-    const int p = c0 + (int)threadIdx.x;
+    const int p = c0 + lane_id();
     const uint32_t cn = c0 + kChunk - 1 <= last_take || p <= last_take ? cand : 0u;
     const int c = cn != 0 ? (int)cn - 1 : 0;
     const uint32_t *o = b32 + (p >> 2);
@@ -463,7 +476,7 @@ __device__ __forceinline__ int encode_block(const uint32_t *b32, int n, uint32_t
 {
     constexpr int NC = kGroup / kChunk;
     static_assert(NC <= 16, "a group's candidates fit one vector");
-    const int lane = threadIdx.x;
+    const int lane = lane_id();
     for (int i = lane; i < (1 << kHashBits) / 4; i += kWave)
         reinterpret_cast<uint4 *>(table)[i] = make_uint4(0, 0, 0, 0);
     wave_sync();
@@ -892,7 +905,7 @@ __device__ __forceinline__ void copy_slot(uint8_t *__restrict__ dst, const uint8
                                           int sz)
 {
     constexpr int kSteps = 4; // 4 KiB per pass of the wave
-    const int lane = threadIdx.x;
+    const int lane = lane_id();
     const int mis = (int)((4 - ((uintptr_t)dst & 3)) & 3);
     const int head = mis < sz ? mis : sz;
     if (lane < head) dst[lane] = src[lane];
@@ -944,12 +957,12 @@ template <int MAXB> struct EncLds {
 // Transpose (and optionally round) the elems x E bytes at src into LDS, then
 // LZ4-encode them into slot; returns the compressed size.  Leaves LDS free
 // for the next block.
-template <int MAXB, int EC, bool ROUND>
+template <int MAXB, int EC, int RM>
 __device__ __forceinline__ int encode_one(const uint8_t *__restrict__ src, int64_t elems, int64_t E,
                                           const RoundParams &rp, int64_t first_elem,
                                           uint8_t *__restrict__ slot, EncLds<MAXB> &L)
 {
-    stage_block<EC, ROUND>(src, elems, E, reinterpret_cast<uint8_t *>(L.blk32), rp, first_elem);
+    stage_block<EC, RM>(src, elems, E, reinterpret_cast<uint8_t *>(L.blk32), rp, first_elem);
     wave_sync();
     const int sz = encode_block<MAXB>(L.blk32, (int)(elems * E), L.table, slot);
     wave_sync();

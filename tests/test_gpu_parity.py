@@ -231,6 +231,64 @@ def test_compress_many_sequences(bsg, E, nb):
     assert np.array_equal(back[: n * E], data)
 
 
+def _segmented_input():
+    # 50,000 blocks of 512 bytes plus a ragged end: three segments of at
+    # least 16,384 blocks, so the encoder runs in segments on two streams
+    # and a third stream packs each finished segment
+    E, nb = 4, 128
+    x = np.concatenate([synth.gen_gauss_int32(nb * 24000, 7, 31),
+                        synth.gen_gauss_int32(nb * 26000 + 45, 2, 32)]).view(np.uint8)
+    return x, E, nb
+
+
+def test_compress_segmented(bsg):
+    """A large input compressed in segments: the stream equals the oracle's;
+    with too little room the call reports the capacity error and writes
+    nothing past the capacity it was given."""
+    x, E, nb = _segmented_input()
+    ref = oracle.compress(x, E, nb)
+    got = host(bsg.compress_sync(dev(x), E, nb))
+    assert got.size == ref.size and np.array_equal(got, ref)
+    for cap in (ref.size - 1, ref.size // 2):
+        big = torch.full((ref.size + 4096,), 0xA5, dtype=torch.uint8, device="cuda:0")
+        _, st = bsg.compress(dev(x), E, nb, out=big[:cap])
+        assert int(host(st)[0]) == -2
+        assert bool((big[cap:] == 0xA5).all())
+
+
+def test_compress_segmented_in_a_graph(bsg):
+    """The segmented compression (which forks onto the library's own streams
+    and joins back) captured in a graph and replayed three times, with
+    other work and synchronisations between the replays: every replay's
+    stream equals the eager one."""
+    x, E, nb = _segmented_input()
+    xd = dev(x)
+    out, nbytes = bsg.compress(xd, E, nb)
+    torch.cuda.synchronize()
+    m = int(nbytes.item())
+    eager = out[:m].clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        out2 = torch.empty_like(out)
+        ws = torch.empty(bsg.workspace_size(x.size // E, E, nb), dtype=torch.uint8, device="cuda:0")
+        nb2 = torch.empty(1, dtype=torch.int64, device="cuda:0")
+        bsg.compress(xd, E, nb, out=out2, workspace=ws, nbytes=nb2, stream=s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        bsg.compress(xd, E, nb, out=out2, workspace=ws, nbytes=nb2, stream=s)
+    for k in range(3):
+        out2.fill_(k)
+        nb2.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(nb2.item()) == m, k
+        assert torch.equal(out2[:m], eager), k
+        _ = (xd[:4096].float() * 2).sum().item()  # eager work between replays
+
+
 def test_pipeline_config0(bsg):
     """Tiny plain pipeline: (16, 36, 64) complex64, f = 0.01, 8 KiB blocks."""
     vis, autos = synth.gen_vis(16, 8, 64, 0, N)
