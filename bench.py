@@ -187,15 +187,23 @@ def main(argv=None):
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
+    # roctx ranges (torch.cuda.nvtx maps to roctx on ROCm): a marker trace
+    # (rocprofv3 --marker-trace) shows each step and its two calls
+    rng = torch.cuda.nvtx.range
+
     def step(evs=None):
-        if evs:
-            evs[0].record(stream)
-        bsg.round_compress(dvis, dautos, w["N"], w["f"], nb, out=out, workspace=ws, nbytes=nbytes)
-        if evs:
-            evs[1].record(stream)
-        bsg.decompress(out, m, n, 4, nb, out=dec, status=status)
-        if evs:
-            evs[2].record(stream)
+        with rng("step"):
+            if evs:
+                evs[0].record(stream)
+            with rng("round_compress"):
+                bsg.round_compress(dvis, dautos, w["N"], w["f"], nb, out=out, workspace=ws,
+                                   nbytes=nbytes)
+            if evs:
+                evs[1].record(stream)
+            with rng("decompress"):
+                bsg.decompress(out, m, n, 4, nb, out=dec, status=status)
+            if evs:
+                evs[2].record(stream)
 
     for _ in range(args.warmup):
         step()

@@ -975,36 +975,31 @@ template <int MAXB> struct DecLds {
     uint32_t buf32[dec_buf_bytes<MAXB>() / 4 + 8 + kWave];
 };
 
-// Decode block b of a stream (payload / off as laid out in the stream) into
-// dst (elems x E bytes).  Returns false when the block is corrupt; then dst
-// holds nothing meaningful.  Never reads past in_end.
-template <int MAXB, int EC>
-__device__ __forceinline__ bool decode_one(const uint8_t *__restrict__ payload, int64_t payload_len,
-                                           const uint64_t *__restrict__ off, int64_t b,
-                                           int64_t elems, int64_t E, const uint8_t *in_end,
-                                           uint8_t *__restrict__ dst, bool fast_out,
-                                           DecLds<MAXB> &L)
+// Stage the LZ4 bytes of block b of a stream (payload / off as laid out in
+// the stream) at the tail of the in-place buffer B (B[-1] readable padding)
+// with the same 4-byte phase as in HBM: the 16-byte lines holding them, one
+// per lane and step (the dwords before the block land in the free output
+// space, the last line's bytes past it in the padding; a line past in_end
+// is read byte by byte).  Returns false when the block's offsets are not
+// plausible; else base / len: where the bytes start in B and how many.
+template <int MAXB>
+__device__ __forceinline__ bool stage_lz4(const uint8_t *__restrict__ payload, int64_t payload_len,
+                                          const uint64_t *__restrict__ off, int64_t b, int ob,
+                                          const uint8_t *in_end, uint32_t *B, int &base, int &len)
 {
     constexpr int kBuf = dec_buf_bytes<MAXB>();
     const int lane = threadIdx.x;
-    const int ob = (int)(elems * E);
     const uint64_t o0 = off[b], o1 = off[b + 1];
     if (o0 > o1 || o1 > (uint64_t)payload_len || o1 - o0 > (uint64_t)lz4_bound(ob)) return false;
-    const int len = (int)(o1 - o0);
-    // stage the LZ4 block at the tail of the buffer with the same 4-byte
-    // phase as in HBM: the 16-byte lines holding it, one per lane and step
-    // (the dwords before the block land in the free output space, the
-    // last line's bytes past it in the padding; a line past in_end is read
-    // byte by byte)
+    len = (int)(o1 - o0);
     const uint8_t *src = payload + o0;
     const int s = (int)((uintptr_t)src & 3);
-    const int base = ((kBuf - len - s) & ~3) + s;
+    base = ((kBuf - len - s) & ~3) + s;
     const int w0 = (base - s) >> 2;            // buffer dword of the stream dword holding src
     const int s16 = (int)((uintptr_t)src & 15);
     const uint4 *s128 = reinterpret_cast<const uint4 *>(src - s16);
     const int lines = (s16 + len + 15) >> 4;
     const int d0 = w0 - ((s16 - s) >> 2);      // buffer dword of the first line's first dword
-    uint32_t *B = L.buf32 + 4; // the decode buffer; B[-1] is readable padding
     for (int k = lane; k < lines; k += kWave) {
         const uint8_t *lp = reinterpret_cast<const uint8_t *>(s128 + k);
         uint4 v;
@@ -1022,6 +1017,23 @@ __device__ __forceinline__ bool decode_one(const uint8_t *__restrict__ payload, 
         d[2] = v.z;
         d[3] = v.w;
     }
+    return true;
+}
+
+// Decode block b of a stream into dst (elems x E bytes).  Returns false
+// when the block is corrupt; then dst holds nothing meaningful.  Never
+// reads past in_end.
+template <int MAXB, int EC>
+__device__ __forceinline__ bool decode_one(const uint8_t *__restrict__ payload, int64_t payload_len,
+                                           const uint64_t *__restrict__ off, int64_t b,
+                                           int64_t elems, int64_t E, const uint8_t *in_end,
+                                           uint8_t *__restrict__ dst, bool fast_out,
+                                           DecLds<MAXB> &L)
+{
+    const int ob = (int)(elems * E);
+    uint32_t *B = L.buf32 + 4; // the decode buffer; B[-1] is readable padding
+    int base, len;
+    if (!stage_lz4<MAXB>(payload, payload_len, off, b, ob, in_end, B, base, len)) return false;
     wave_sync();
     const bool ok = decode_inplace(B, base, base + len, ob);
     wave_sync();
