@@ -1035,7 +1035,11 @@ __device__ __forceinline__ bool decode_one(const uint8_t *__restrict__ payload, 
     int base, len;
     if (!stage_lz4<MAXB>(payload, payload_len, off, b, ob, in_end, B, base, len)) return false;
     wave_sync();
+    // the serial token walk issues ahead of other waves' staging and
+    // inverse transposes, which have independent work to fill the gaps
+    __builtin_amdgcn_s_setprio(1);
     const bool ok = decode_inplace(B, base, base + len, ob);
+    __builtin_amdgcn_s_setprio(0);
     wave_sync();
     if (ok) unstage_block<EC>(reinterpret_cast<const uint8_t *>(B), elems, E, dst, fast_out);
     wave_sync();
