@@ -6,7 +6,9 @@ output bytes:
 * waves_per_cu, the workgroups per compute unit in the grid (each workgroup
   is one wavefront working on one block at a time, its block and hash
   table in LDS).  Fewer leave latency uncovered; more than LDS lets reside
-  at once queue behind the first round, which balances the tail.
+  at once queue behind the first round, which balances the tail, and at the
+  top of the range every workgroup takes only a few blocks (the hardware
+  dispatcher then balances the load as for one workgroup per block).
 * schedule, how the blocks of an element class are dealt to workgroups:
   every grid-th block (strided) or one contiguous range per workgroup
   (ranges), which walks the chunk table one entry at a time instead of
@@ -25,7 +27,7 @@ import statistics
 
 import torch
 
-WAVES = (4, 8, 16, 32, 64, 128)
+WAVES = (4, 8, 16, 32, 64, 128, 256, 1024, 8192)
 SCHEDULES = (0, 1)  # BSG_SCHED_STRIDED, BSG_SCHED_RANGES
 CANDIDATES = tuple((w, s) for s in SCHEDULES for w in WAVES)
 
