@@ -17,7 +17,9 @@ namespace bsg {
 
 namespace {
 
-constexpr int kMaxClasses = 16;
+constexpr int kMaxClasses = kSideEvents; // (one encode event per class)
+// a batch of at least this many blocks splits its classes over two streams
+constexpr int64_t kBatchSideMinBlocks = 16384;
 
 struct BatchHeader {
     int32_t count, n_classes;
@@ -184,23 +186,27 @@ __global__ __launch_bounds__(64) void k_batch_dec_tail(const uint8_t *__restrict
     for (int64_t i = threadIdx.x; i < tail_bytes; i += kWave) dst[i] = ch.in[table_end + payload_len + i];
 }
 
-// ---- global exclusive prefix of the block sizes ---------------------------
-__global__ __launch_bounds__(256) void k_btile_sum(const int32_t *__restrict__ sizes, int64_t n,
-                                                   int64_t *__restrict__ tile_sum)
+// ---- exclusive prefix of the block sizes, one element class at a time ----
+// Blocks [b0, b0 + n) (a class); tile k holds blocks b0 + k kTile .. .
+__global__ __launch_bounds__(256) void k_btile_sum(const int32_t *__restrict__ sizes, int64_t b0,
+                                                   int64_t n, int64_t *__restrict__ tile_sum)
 {
     __shared__ int64_t sh[256];
     const int64_t base = int64_t(blockIdx.x) * kTile;
     int64_t s = 0;
     for (int k = threadIdx.x; k < kTile; k += 256)
-        if (base + k < n) s += sizes[base + k];
+        if (base + k < n) s += sizes[b0 + base + k];
     const int64_t inc = block_sum_i64(s, sh);
     if (threadIdx.x == 255) tile_sum[blockIdx.x] = inc;
 }
 
-__global__ __launch_bounds__(256) void k_btile_scan(int64_t *__restrict__ tile_sum, int64_t n_tiles)
+// In place, after the bytes of the classes before (*carry, 0 for the
+// first); leaves the bytes up to the end of this class in *carry.
+__global__ __launch_bounds__(256) void k_btile_scan(int64_t *__restrict__ tile_sum, int64_t n_tiles,
+                                                    int64_t *__restrict__ carry_io, int first)
 {
     __shared__ int64_t sh[256];
-    int64_t carry = 0;
+    int64_t carry = first ? 0 : *carry_io;
     for (int64_t base = 0; base < n_tiles; base += 256) {
         const int64_t k = base + threadIdx.x;
         const int64_t v = k < n_tiles ? tile_sum[k] : 0;
@@ -209,10 +215,11 @@ __global__ __launch_bounds__(256) void k_btile_scan(int64_t *__restrict__ tile_s
         carry += sh[255];
         __syncthreads();
     }
+    if (threadIdx.x == 0) *carry_io = carry;
 }
 
-__global__ __launch_bounds__(256) void k_bprefix(const int32_t *__restrict__ sizes, int64_t n,
-                                                 const int64_t *__restrict__ tile_off,
+__global__ __launch_bounds__(256) void k_bprefix(const int32_t *__restrict__ sizes, int64_t b0,
+                                                 int64_t n, const int64_t *__restrict__ tile_off,
                                                  int64_t *__restrict__ prefix)
 {
     __shared__ int64_t sh[256];
@@ -222,26 +229,26 @@ __global__ __launch_bounds__(256) void k_bprefix(const int32_t *__restrict__ siz
     int64_t s = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        v[k] = base + k < n ? sizes[base + k] : 0;
+        v[k] = base + k < n ? sizes[b0 + base + k] : 0;
         s += v[k];
     }
     const int64_t inc = block_sum_i64(s, sh);
     int64_t o = tile_off[blockIdx.x] + inc - s;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        if (base + k <= n) prefix[base + k] = o; // prefix[n] = total
+        if (base + k <= n) prefix[b0 + base + k] = o; // prefix[b0 + n] = end of the class
         o += v[k];
     }
 }
 
 // One wavefront per chunk: stream length and capacity verdict, header,
 // offsets table and raw tail.
-__global__ __launch_bounds__(64) void k_batch_finish(const uint8_t *__restrict__ table,
+__global__ __launch_bounds__(64) void k_batch_finish(const uint8_t *__restrict__ table, int chunk0,
                                                      const int64_t *__restrict__ prefix,
                                                      int64_t *__restrict__ d_nbytes)
 {
     const TableView T(table);
-    const BatchChunk &ch = T.ch[blockIdx.x];
+    const BatchChunk &ch = T.ch[chunk0 + blockIdx.x];
     const int lane = threadIdx.x;
     const int64_t base = prefix[ch.block_start];
     const int64_t pay = prefix[ch.block_start + ch.n_blocks] - base;
@@ -264,18 +271,19 @@ __global__ __launch_bounds__(64) void k_batch_finish(const uint8_t *__restrict__
     for (int64_t i = lane; i < tail_bytes; i += kWave) tdst[i] = tsrc[i];
 }
 
-// Every block's LZ4 bytes from its slot to its place in its chunk's stream.
-__global__ __launch_bounds__(64) void k_batch_pack(const uint8_t *__restrict__ table,
+// The LZ4 bytes of a class's blocks from their slots to their places in
+// their chunks' streams.
+__global__ __launch_bounds__(64) void k_batch_pack(const uint8_t *__restrict__ table, int cls,
                                                    const uint8_t *__restrict__ slots,
                                                    const int32_t *__restrict__ sizes,
                                                    const int64_t *__restrict__ prefix,
                                                    const int64_t *__restrict__ d_nbytes)
 {
     const TableView T(table);
-    const int64_t total = T.h->total_blocks;
-    const int count = T.h->count;
-    for (int64_t g = blockIdx.x; g < total; g += gridDim.x) {
-        const int c = find_chunk(T.ch, 0, count - 1, g);
+    const BatchClass C = T.cls[cls];
+    const int last = C.first_chunk + C.n_chunks - 1;
+    for (int64_t g = C.first_block + blockIdx.x; g < C.first_block + C.n_blocks; g += gridDim.x) {
+        const int c = find_chunk(T.ch, C.first_chunk, last, g);
         const BatchChunk &ch = T.ch[c];
         if (d_nbytes[ch.orig] < 0) continue;
         const int64_t local = g - ch.block_start;
@@ -348,7 +356,7 @@ hipError_t bdec_dispatch(int ec, const uint8_t *t, int cls, int64_t nblk, int wp
 }
 
 struct WsLayout {
-    int64_t slots, sizes, prefix, tiles, total;
+    int64_t slots, sizes, prefix, tiles, carry, total;
 };
 
 WsLayout ws_layout(const BatchHeader &h)
@@ -360,7 +368,8 @@ WsLayout ws_layout(const BatchHeader &h)
     w.sizes = up(h.slot_total);
     w.prefix = w.sizes + up(4 * h.total_blocks);
     w.tiles = w.prefix + up(8 * (h.total_blocks + 1 + kTile));
-    w.total = w.tiles + up(8 * (n_tiles + 1));
+    w.carry = w.tiles + up(8 * (n_tiles + 1));
+    w.total = w.carry + 256;
     return w;
 }
 
@@ -474,28 +483,54 @@ int bsg_batch_compress(const void *host_table, const void *d_table, int64_t *d_n
     int32_t *sizes = reinterpret_cast<int32_t *>(ws + w.sizes);
     int64_t *prefix = reinterpret_cast<int64_t *>(ws + w.prefix);
     int64_t *tiles = reinterpret_cast<int64_t *>(ws + w.tiles);
-    hipError_t e = hipSuccess;
-    for (int c = 0; c < h.n_classes && e == hipSuccess; ++c) {
+    int64_t *carry = reinterpret_cast<int64_t *>(ws + w.carry);
+    // Class by class: the encode on the caller's stream or (every other
+    // class) the library's encode stream; then on the pack stream the
+    // class's scan (after the bytes of the classes before), finish and pack,
+    // which run beside the next classes' encodes.
+    int nonempty = 0;
+    for (int c = 0; c < h.n_classes; ++c) nonempty += T.cls[c].n_blocks > 0;
+    std::unique_lock<std::mutex> lock;
+    SideStreams *g = nullptr;
+    if (nonempty >= 2 && h.total_blocks >= kBatchSideMinBlocks &&
+        side_streams_begin(s, lock, &g) != hipSuccess)
+        return BSG_EHIP;
+    hipStream_t ps = g ? g->pack : s;
+    int i = 0, last_enc = -1;
+    for (int c = 0; c < h.n_classes; ++c) {
         const BatchClass &C = T.cls[c];
-        if (C.n_blocks == 0) continue;
-        e = C.small ? benc_dispatch<kSmallBlock>(C.ec, t, c, C.n_blocks, waves_per_cu, schedule,
-                                                 slots, sizes, s)
-                    : benc_dispatch<kLargeBlock>(C.ec, t, c, C.n_blocks, waves_per_cu, schedule,
-                                                 slots, sizes, s);
+        if (C.n_blocks > 0) {
+            hipStream_t es = (g && (i & 1)) ? g->enc : s;
+            const hipError_t e =
+                C.small ? benc_dispatch<kSmallBlock>(C.ec, t, c, C.n_blocks, waves_per_cu,
+                                                     schedule, slots, sizes, es)
+                        : benc_dispatch<kLargeBlock>(C.ec, t, c, C.n_blocks, waves_per_cu,
+                                                     schedule, slots, sizes, es);
+            if (e != hipSuccess) return BSG_EHIP;
+            if (g) {
+                if (hipEventRecord(g->done[i], es) != hipSuccess ||
+                    hipStreamWaitEvent(ps, g->done[i], 0) != hipSuccess)
+                    return BSG_EHIP;
+                if (i & 1) last_enc = i;
+            }
+            ++i;
+        }
+        const int64_t nt = (C.n_blocks + kTile - 1) / kTile + 1; // + room for the class's end
+        hipLaunchKernelGGL(k_btile_sum, dim3((unsigned)nt), dim3(256), 0, ps, sizes, C.first_block,
+                           C.n_blocks, tiles);
+        hipLaunchKernelGGL(k_btile_scan, dim3(1), dim3(256), 0, ps, tiles, nt, carry, c == 0 ? 1 : 0);
+        hipLaunchKernelGGL(k_bprefix, dim3((unsigned)nt), dim3(256), 0, ps, sizes, C.first_block,
+                           C.n_blocks, tiles, prefix);
+        if (C.n_chunks > 0)
+            hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)C.n_chunks), dim3(kWave), 0, ps, t,
+                               C.first_chunk, prefix, d_nbytes);
+        if (C.n_blocks > 0)
+            hipLaunchKernelGGL(k_batch_pack, dim3((unsigned)persistent_grid(C.n_blocks, waves_per_cu)),
+                               dim3(kWave), 0, ps, t, c, slots, sizes, prefix, d_nbytes);
+        if (hipGetLastError() != hipSuccess) return BSG_EHIP;
     }
-    if (e != hipSuccess) return BSG_EHIP;
-    const int64_t n_tiles = (h.total_blocks + kTile - 1) / kTile + 1; // + room for prefix[total]
-    hipLaunchKernelGGL(k_btile_sum, dim3((unsigned)n_tiles), dim3(256), 0, s, sizes, h.total_blocks,
-                       tiles);
-    hipLaunchKernelGGL(k_btile_scan, dim3(1), dim3(256), 0, s, tiles, n_tiles);
-    hipLaunchKernelGGL(k_bprefix, dim3((unsigned)n_tiles), dim3(256), 0, s, sizes, h.total_blocks,
-                       tiles, prefix);
-    hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)h.count), dim3(kWave), 0, s, t, prefix,
-                       d_nbytes);
-    if (h.total_blocks > 0)
-        hipLaunchKernelGGL(k_batch_pack, dim3((unsigned)persistent_grid(h.total_blocks, waves_per_cu)),
-                           dim3(kWave), 0, s, t, slots, sizes, prefix, d_nbytes);
-    return hip_status(hipGetLastError());
+    if (g && side_streams_end(g, s, last_enc) != hipSuccess) return BSG_EHIP;
+    return BSG_OK;
 }
 
 int bsg_batch_decompress(const void *host_table, const void *d_table, int32_t *d_status,

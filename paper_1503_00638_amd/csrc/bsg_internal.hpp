@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "bsg.h"
 
 namespace bsg {
@@ -182,6 +184,24 @@ hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int
                            const RoundParams *rp, hipStream_t s, int filter = BSG_FILTER_BIT,
                            bool may_segment = true);
 int64_t compress_workspace(const Layout &L);
+
+// Two streams of the library's own per device, an encode stream and a pack
+// stream (default priority), with their events, made once.  Work split over
+// them runs beside the caller's stream: side_streams_begin locks the
+// current device's set (the lock stays held while the caller enqueues, so
+// calls from several host threads do not interleave their use of the
+// events) and makes both streams wait for the caller's work so far;
+// side_streams_end makes the caller's stream wait for the pack stream and
+// for event done[last_enc] of the encode stream.
+constexpr int kSideEvents = 16;
+struct SideStreams {
+    bool made = false, ok = false;
+    hipStream_t enc = nullptr, pack = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, done[kSideEvents] = {};
+};
+hipError_t side_streams_begin(hipStream_t s, std::unique_lock<std::mutex> &lock,
+                              SideStreams **out);
+hipError_t side_streams_end(SideStreams *g, hipStream_t s, int last_enc);
 hipError_t launch_decompress(const uint8_t *in, int64_t in_nbytes, uint8_t *out,
                              const Layout &L, int32_t *d_status, hipStream_t s, int filter = BSG_FILTER_BIT);
 

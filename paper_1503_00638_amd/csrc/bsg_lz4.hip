@@ -13,8 +13,6 @@
 // copy by HBM).
 // Decompression = k_decode (stage the LZ4 block in LDS, decode into LDS,
 // inverse transpose on the way out to HBM).
-#include <mutex>
-
 #include "bsg_lz4_dev.hpp"
 
 namespace bsg {
@@ -258,36 +256,53 @@ int64_t compress_workspace(const Layout &L)
     return ws;
 }
 
-// Streams and events of one device for the segmented compression, made
-// once (default priority).  Guarded by seg_mu, which is held while a call
-// enqueues its work, so calls from several host threads do not interleave
-// their use of the shared events.
-constexpr int kMaxSeg = 16;                // segments of a large input
-constexpr int64_t kSegMinBlocks = 8192;    // ... of at least this many blocks
-struct SegStreams {
-    bool made = false, ok = false;
-    hipStream_t enc = nullptr, pack = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr, done[kMaxSeg] = {};
-};
-constexpr int kMaxSegDevices = 64;
-std::mutex seg_mu;
-SegStreams seg_dev[kMaxSegDevices]; // guarded by seg_mu
+constexpr int kMaxSeg = kSideEvents;     // segments of a large input
+constexpr int64_t kSegMinBlocks = 8192; // ... of at least this many blocks
 
-SegStreams *seg_streams_locked(int dev)
+namespace {
+constexpr int kMaxSideDevices = 64;
+std::mutex side_mu;
+SideStreams side_dev[kMaxSideDevices]; // guarded by side_mu
+} // namespace
+
+hipError_t side_streams_begin(hipStream_t s, std::unique_lock<std::mutex> &lock,
+                              SideStreams **out)
 {
-    if (dev < 0 || dev >= kMaxSegDevices) return nullptr;
-    SegStreams &g = seg_dev[dev];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxSideDevices) return hipErrorInvalidDevice;
+    lock = std::unique_lock<std::mutex>(side_mu);
+    SideStreams &g = side_dev[dev];
     if (!g.made) {
         g.made = true;
         bool ok = hipStreamCreateWithFlags(&g.enc, hipStreamNonBlocking) == hipSuccess &&
                   hipStreamCreateWithFlags(&g.pack, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&g.fork, hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&g.join, hipEventDisableTiming) == hipSuccess;
-        for (int i = 0; ok && i < kMaxSeg; ++i)
+        for (int i = 0; ok && i < kSideEvents; ++i)
             ok = hipEventCreateWithFlags(&g.done[i], hipEventDisableTiming) == hipSuccess;
         g.ok = ok;
     }
-    return g.ok ? &g : nullptr;
+    if (!g.ok) return hipErrorOutOfMemory;
+    if ((e = hipEventRecord(g.fork, s)) != hipSuccess ||
+        (e = hipStreamWaitEvent(g.enc, g.fork, 0)) != hipSuccess ||
+        (e = hipStreamWaitEvent(g.pack, g.fork, 0)) != hipSuccess)
+        return e;
+    *out = &g;
+    return hipSuccess;
+}
+
+// (the encode stream is also joined directly, so that a stream capture sees
+// it joined)
+hipError_t side_streams_end(SideStreams *g, hipStream_t s, int last_enc)
+{
+    hipError_t e;
+    if ((e = hipEventRecord(g->join, g->pack)) != hipSuccess ||
+        (e = hipStreamWaitEvent(s, g->join, 0)) != hipSuccess)
+        return e;
+    if (last_enc >= 0 && (e = hipStreamWaitEvent(s, g->done[last_enc], 0)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
 hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int64_t cap,
@@ -316,20 +331,10 @@ hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int
     // segments of whole tiles
     int nseg = (int)std::min<int64_t>(kMaxSeg, L.n_blocks / kSegMinBlocks);
     if (nseg < 1 || !may_segment) nseg = 1;
-    std::unique_lock<std::mutex> lock(seg_mu, std::defer_lock);
-    SegStreams *g = nullptr;
+    std::unique_lock<std::mutex> lock;
+    SideStreams *g = nullptr;
     hipError_t e;
-    if (nseg > 1) {
-        int dev = 0;
-        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-        lock.lock();
-        g = seg_streams_locked(dev);
-        if (!g) return hipErrorOutOfMemory;
-        if ((e = hipEventRecord(g->fork, s)) != hipSuccess ||
-            (e = hipStreamWaitEvent(g->enc, g->fork, 0)) != hipSuccess ||
-            (e = hipStreamWaitEvent(g->pack, g->fork, 0)) != hipSuccess)
-            return e;
-    }
+    if (nseg > 1 && (e = side_streams_begin(s, lock, &g)) != hipSuccess) return e;
     hipStream_t ps = g ? g->pack : s;
     for (int i = 0; i < nseg; ++i) {
         const int64_t t0 = n_tiles * i / nseg, t1 = n_tiles * (i + 1) / nseg;
@@ -364,13 +369,8 @@ hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
-    // join both internal streams back into the caller's (the encode stream
-    // also directly, so that a stream capture sees it joined)
-    if (g && ((e = hipEventRecord(g->join, ps)) != hipSuccess ||
-              (e = hipStreamWaitEvent(s, g->join, 0)) != hipSuccess ||
-              (e = hipStreamWaitEvent(s, g->done[(nseg & 1) ? nseg - 2 : nseg - 1], 0)) !=
-                  hipSuccess))
-        return e;
+    // (odd segments went to the encode stream)
+    if (g) return side_streams_end(g, s, (nseg & 1) ? nseg - 2 : nseg - 1);
     return hipSuccess;
 }
 
