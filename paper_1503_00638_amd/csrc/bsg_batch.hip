@@ -141,7 +141,7 @@ __global__ __launch_bounds__(64) void k_batch_encode(const uint8_t *__restrict__
 }
 
 template <int MAXB, int EC>
-__global__ __launch_bounds__(64) void k_batch_decode(const uint8_t *__restrict__ table, int cls,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(dec_waves_per_eu<MAXB, EC>()))) void k_batch_decode(const uint8_t *__restrict__ table, int cls,
                                                      int32_t *__restrict__ status, int schedule)
 {
     __shared__ DecLds<MAXB> L;

@@ -164,7 +164,7 @@ struct DecArgs {
 };
 
 template <int MAXB, int EC>
-__global__ __launch_bounds__(64) void k_decode(DecArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(dec_waves_per_eu<MAXB, EC>()))) void k_decode(DecArgs a)
 {
     __shared__ DecLds<MAXB> L;
     const int lane = threadIdx.x;
@@ -221,6 +221,39 @@ hipError_t encode_dispatch(const EncArgs &ea, int64_t nblocks, const RoundParams
     }
 }
 
+// VGPRs of an encoder instance (from its kernel attributes, read once).
+template <int MAXB, int EC, int RM> int encoder_vgprs()
+{
+    static const int regs = [] {
+        hipFuncAttributes a{};
+        return hipFuncGetAttributes(&a, reinterpret_cast<const void *>(&k_encode<MAXB, EC, RM>)) ==
+                       hipSuccess
+                   ? a.numRegs
+                   : 1 << 20;
+    }();
+    return regs;
+}
+
+// The VGPRs of the instance encode_dispatch picks.
+template <int MAXB> int encoder_vgprs_for(const RoundParams *rp, int ec)
+{
+    if (rp) {
+        if (ec != 4) return encoder_vgprs<MAXB, 0, kRoundPlain>();
+        return rp->fscale ? encoder_vgprs<MAXB, 4, kRoundScaled>()
+                          : encoder_vgprs<MAXB, 4, kRoundPlain>();
+    }
+    switch (ec) {
+    case kByteShuffle: return encoder_vgprs<MAXB, kByteShuffle, kRoundNone>();
+    case 1: return encoder_vgprs<MAXB, 1, kRoundNone>();
+    case 2: return encoder_vgprs<MAXB, 2, kRoundNone>();
+    case 4: return encoder_vgprs<MAXB, 4, kRoundNone>();
+    case 8: return encoder_vgprs<MAXB, 8, kRoundNone>();
+    case 12: return encoder_vgprs<MAXB, 12, kRoundNone>();
+    case 16: return encoder_vgprs<MAXB, 16, kRoundNone>();
+    default: return encoder_vgprs<MAXB, 0, kRoundNone>();
+    }
+}
+
 template <int MAXB, int EC>
 hipError_t decode_launch(const DecArgs &a, hipStream_t s)
 {
@@ -258,6 +291,11 @@ int64_t compress_workspace(const Layout &L)
 
 constexpr int kMaxSeg = kSideEvents;     // segments of a large input
 constexpr int64_t kSegMinBlocks = 8192; // ... of at least this many blocks
+// Segments pay only when the encoder leaves registers for the pack waves
+// beside its 4 resident waves per SIMD (LDS allows 16 per CU): at 112 VGPRs
+// or fewer.  An encoder that fills the register file (125 VGPRs for 8-byte
+// elements) lost 14 % to them, one at 84 gained 4 %.
+constexpr int kSegMaxVgprs = 112;
 
 namespace {
 constexpr int kMaxSideDevices = 64;
@@ -330,6 +368,11 @@ hipError_t launch_compress(const uint8_t *in, uint8_t *out, const Layout &L, int
 
     // segments of whole tiles
     int nseg = (int)std::min<int64_t>(kMaxSeg, L.n_blocks / kSegMinBlocks);
+    if (nseg > 1 && may_segment) {
+        const int regs = L.block_bytes() <= kSmallBlock ? encoder_vgprs_for<kSmallBlock>(rp, ec)
+                                                        : encoder_vgprs_for<kLargeBlock>(rp, ec);
+        if (regs > kSegMaxVgprs) nseg = 1;
+    }
     if (nseg < 1 || !may_segment) nseg = 1;
     std::unique_lock<std::mutex> lock;
     SideStreams *g = nullptr;

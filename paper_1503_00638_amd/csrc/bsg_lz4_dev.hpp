@@ -969,6 +969,16 @@ __device__ __forceinline__ int encode_one(const uint8_t *__restrict__ src, int64
     return sz;
 }
 
+// Waves per SIMD the decoder kernels ask the register allocator for: 4
+// (at most 128 VGPRs) for 8 KiB blocks of element classes up to 8 bytes,
+// where LDS lets 18 blocks reside per CU and one more register would cost
+// a quarter of them; 1 (no limit) where the transpose of 12- and 16-byte
+// elements needs more registers or LDS already allows only a few blocks.
+template <int MAXB, int EC> constexpr int dec_waves_per_eu()
+{
+    return MAXB <= kSmallBlock && EC != 12 && EC != 16 ? 4 : 1;
+}
+
 template <int MAXB> struct DecLds {
     // + 4 dwords in front (one readable padding dword before the buffer),
     // 4 over-read after, and 64 for the copy lanes past a range
