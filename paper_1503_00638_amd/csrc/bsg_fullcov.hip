@@ -6,7 +6,7 @@
 // G2 = 12 f s_k^2.  With Q = 2N C this is G2 = c / (Q^-1)_kk, c = (12 f)/(2N).
 //
 // One workgroup per sample holds Q in LDS (D = I^2 <= 121, so at most
-// 117 KiB): the Hermitian V of the sample, Q from it, a right-looking
+// 120 KiB): the Hermitian V of the sample, Q from it, a right-looking
 // Cholesky factorisation Q = L L^T in place (a step per column, the
 // trailing update spread over the workgroup), then M = L^-1 one column per
 // thread (stored transposed in the free upper triangle) and
@@ -23,7 +23,7 @@ namespace bsg {
 
 namespace {
 
-constexpr int kMaxInputs = 11; // D = 121 degrees of freedom, 117 KiB of LDS
+constexpr int kMaxInputs = 11; // D = 121 degrees of freedom, 120 KiB of LDS
 
 struct Cplx {
     double re, im;
@@ -59,9 +59,14 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
 {
     extern __shared__ double smem[];
     const int D = a.D, I = a.I, P = a.P;
-    double *Q = smem;                     // D x D, row major
-    double *Mdiag = Q + D * D;            // D
-    Cplx *V = reinterpret_cast<Cplx *>(Mdiag + D); // I x I
+    // Q: D x D, row major with rows of LD doubles, LD even: the inverse's
+    // lanes walk rows LD + 1 doubles apart (an odd stride spreads them over
+    // the LDS banks); the factorisation reads column k from its copy colk
+    const int LD = D + (D & 1);
+    double *Q = smem;
+    double *Mdiag = Q + D * LD;           // D
+    double *colk = Mdiag + D;             // D: column k of L during step k
+    Cplx *V = reinterpret_cast<Cplx *>(colk + D); // I x I
     int *dof = reinterpret_cast<int *>(V + I * I);  // D: product * 2 + (Im ? 1 : 0)
     __shared__ int bad;
     const int tid = threadIdx.x;
@@ -116,27 +121,34 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
             const Cplx B2 = mul_conj(V[g * I + j], V[h * I + i]);
             q = -A2.im + B2.im;
         }
-        Q[e] = q;
+        Q[x * LD + y] = q;
     }
     __syncthreads();
 
     // Cholesky, right-looking, in place in the lower triangle
     for (int k = 0; k < D; ++k) {
-        const double d = Q[k * D + k];
+        const double d = Q[k * LD + k];
         if (!(d > 0.0) || d == __builtin_inf()) { // uniform: every thread reads the same d
             if (tid == 0) bad = 1;
             break;
         }
         const double lkk = sqrt(d);
         __syncthreads(); // everyone has read Q[k][k]
-        if (tid == 0) Q[k * D + k] = lkk;
-        for (int i = k + 1 + tid; i < D; i += blockDim.x) Q[i * D + k] = Q[i * D + k] / lkk;
+        if (tid == 0) Q[k * LD + k] = lkk;
+        for (int i = k + 1 + tid; i < D; i += blockDim.x) {
+            const double lik = Q[i * LD + k] / lkk;
+            Q[i * LD + k] = lik;
+            colk[i] = lik;
+        }
         __syncthreads();
         // trailing lower triangle, rows and columns k+1 .. D-1, on a 16 x 16
         // grid of threads
-        for (int i = k + 1 + (tid >> 4); i < D; i += 16)
+        for (int i = k + 1 + (tid >> 4); i < D; i += 16) {
+            const double lik = colk[i];
+#pragma unroll 4
             for (int j = k + 1 + (tid & 15); j <= i; j += 16)
-                Q[i * D + j] = Q[i * D + j] - Q[i * D + k] * Q[j * D + k];
+                Q[i * LD + j] = Q[i * LD + j] - lik * colk[j];
+        }
         __syncthreads();
     }
     __syncthreads();
@@ -146,18 +158,22 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
     double qk = __builtin_nan("");
     if (!failed) {
         for (int j = tid; j < D; j += blockDim.x) {
-            const double mjj = 1.0 / Q[j * D + j];
+            const double mjj = 1.0 / Q[j * LD + j];
             Mdiag[j] = mjj;
             for (int i = j + 1; i < D; ++i) {
-                double acc = Q[i * D + j] * mjj;
-                for (int m = j + 1; m < i; ++m) acc = acc + Q[i * D + m] * Q[j * D + m];
-                const double mij = -acc / Q[i * D + i];
-                Q[j * D + i] = mij;
+                double acc = Q[i * LD + j] * mjj;
+                // (unrolled so that the loads of later terms issue ahead;
+                // the terms are still added one by one, in order)
+#pragma unroll 8
+                for (int m = j + 1; m < i; ++m) acc = acc + Q[i * LD + m] * Q[j * LD + m];
+                const double mij = -acc / Q[i * LD + i];
+                Q[j * LD + i] = mij;
             }
             // (Q^-1)_jj = sum_{i >= j} M_ij^2 in increasing i
             double q = 0.0;
             q = q + mjj * mjj;
-            for (int i = j + 1; i < D; ++i) q = q + Q[j * D + i] * Q[j * D + i];
+#pragma unroll 8
+            for (int i = j + 1; i < D; ++i) q = q + Q[j * LD + i] * Q[j * LD + i];
             if (j == tid) qk = q;
             if (a.qdiag) a.qdiag[s * D + j] = q;
         }
@@ -191,7 +207,8 @@ hipError_t launch_fullcov(const float *vis, const float *autos, int64_t F, int64
     if (F * T == 0 || D == 0) return hipSuccess;
     FullcovArgs a{reinterpret_cast<const float2 *>(vis), autos, F, T, (int)I, P, D, c,
                   reinterpret_cast<float2 *>(vis_out), qdiag};
-    const size_t lds = sizeof(double) * ((size_t)D * D + D) + sizeof(Cplx) * (size_t)(I * I) +
+    const size_t lds = sizeof(double) * ((size_t)D * (D + (D & 1)) + 2 * D) +
+                       sizeof(Cplx) * (size_t)(I * I) +
                        sizeof(int) * (size_t)D;
     hipLaunchKernelGGL(k_fullcov, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
     return hipGetLastError();
