@@ -232,3 +232,35 @@ def test_batch_decompress_graph_replay(bsg):
         assert not host(dplan.status).any(), rep
         for k, d in enumerate(data):
             assert np.array_equal(host(dplan.outs[k])[: d.size], d), (rep, k)
+
+
+def test_batch_side_streams_graph_replay(bsg):
+    """A batch of more than 16384 blocks in several element classes splits
+    its classes over the library's own streams (each class scanned,
+    finished and packed while the next one encodes).  Captured in a graph,
+    it replays to the eager bytes three times, with other work and
+    synchronisations between the replays."""
+    specs = [(4, 2048, 2048 * 9000 + 5), (2, 4096, 4096 * 8000 + 8), (1, 8192, 8192 * 10 + 3)]
+    data = [chunk_data(k, E, n) for k, (E, _, n) in enumerate(specs)]
+    Es = [E for E, _, _ in specs]
+    Bs = [b for _, b, _ in specs]
+    xs = [to_dev(d) for d in data]
+    plan = bsg.BatchPlan.for_compress(xs, Es, Bs)
+    nb0 = host(plan.compress()).copy()
+    eager = [host(o)[: int(m)].copy() for o, m in zip(plan.outs, nb0)]
+    for k in (1, 2):  # the smaller chunks against the oracle as well
+        assert np.array_equal(eager[k], oracle.compress(data[k], Es[k], Bs[k])), k
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.compress()
+    for rep in range(3):
+        for o in plan.outs:
+            o.fill_(rep)
+        plan.nbytes.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(plan.nbytes), nb0), rep
+        for k, o in enumerate(plan.outs):
+            assert np.array_equal(host(o)[: int(nb0[k])], eager[k]), (rep, k)
+        _ = (xs[0][:4096].float() * 2).sum().item()  # other work between replays
