@@ -554,3 +554,34 @@ def test_repeatable_and_stream_order(bsg):
             torch.cuda.synchronize()
             outs.append(host(o)[: int(host(nb)[0])])
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
+
+
+def test_compress_segmented_two_threads(bsg):
+    """Two host threads compress large inputs at the same time, each on its
+    own stream: the library's side streams and their events are shared and
+    taken in turn, and both streams come out equal to the oracle's."""
+    import threading
+    x, E, nb = _segmented_input()
+    y = x[::-1].copy()
+    refs = [oracle.compress(x, E, nb), oracle.compress(y, E, nb)]
+    xs = [dev(x), dev(y)]
+    torch.cuda.synchronize()
+    outs = [None, None]
+
+    def work(k):
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            for _ in range(3):
+                o, m = bsg.compress(xs[k], E, nb, stream=s)
+            s.synchronize()
+            outs[k] = (o, m)
+
+    th = [threading.Thread(target=work, args=(k,)) for k in (0, 1)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for k in (0, 1):
+        o, m = outs[k]
+        n = int(host(m)[0])
+        assert n == refs[k].size and np.array_equal(host(o)[:n], refs[k]), k
