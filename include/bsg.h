@@ -312,6 +312,10 @@ int64_t bsg_batch_workspace_size(const void *host_table);
  * out holds nothing meaningful; the other chunks are unaffected).
  * workspace: 256-byte aligned, workspace_bytes >= bsg_batch_workspace_size.
  * waves_per_cu, schedule: the launch shape (above).
+ * stream: a batch of 16384 blocks or more in two or more element classes
+ *   encodes its classes alternately on this stream and on the library's
+ *   encode stream, while the library's pack stream scans, finishes and packs
+ *   each class (the streams of bsg_compress_lz4, joined back into this one).
  * Errors: BSG_EINVAL (NULL pointers, misaligned buffers, unknown schedule),
  *   BSG_ECAPACITY (workspace too small), BSG_EHIP (launch failure). */
 int bsg_batch_compress(const void *host_table, const void *d_table, int64_t *d_nbytes,
