@@ -143,9 +143,73 @@ constexpr int kByteShuffle = -1;
 
 // Lanes take 4 elements at a time, so every LDS access is one aligned dword
 // (elems is a multiple of 8).
+// Byte shuffle of elements whose size is a multiple of 4 (E <= 16), the
+// input 16-byte aligned: each lane loads 4 elements (4E bytes) with 16-byte
+// loads, and every 4 x 4 byte sub-matrix (dword kg of the 4 elements) is
+// transposed in registers into dword g of planes 4kg .. 4kg + 3.
+template <int E>
+__device__ __forceinline__ void block_forward_bytes_fast(const uint8_t *__restrict__ in,
+                                                         uint8_t *lds, int64_t elems)
+{
+    constexpr int W = E / 4; // dwords per element
+    uint32_t *l32 = reinterpret_cast<uint32_t *>(lds);
+    const int64_t pw = elems / 4; // dwords per plane
+    for (int64_t g = lane_id(); g < elems / 4; g += kWave) {
+        const uint4 *s4 = reinterpret_cast<const uint4 *>(in + 4 * g * E);
+        uint32_t w[4 * W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const uint4 v = s4[q];
+            w[4 * q] = v.x;
+            w[4 * q + 1] = v.y;
+            w[4 * q + 2] = v.z;
+            w[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int kg = 0; kg < W; ++kg) {
+            uint32_t o0, o1, o2, o3;
+            byte_transpose4(w[kg], w[W + kg], w[2 * W + kg], w[3 * W + kg], o0, o1, o2, o3);
+            l32[(4 * kg) * pw + g] = o0;
+            l32[(4 * kg + 1) * pw + g] = o1;
+            l32[(4 * kg + 2) * pw + g] = o2;
+            l32[(4 * kg + 3) * pw + g] = o3;
+        }
+    }
+}
+
+template <int E>
+__device__ __forceinline__ void block_inverse_bytes_fast(const uint8_t *lds,
+                                                         uint8_t *__restrict__ out, int64_t elems)
+{
+    constexpr int W = E / 4;
+    const uint32_t *l32 = reinterpret_cast<const uint32_t *>(lds);
+    const int64_t pw = elems / 4;
+    for (int64_t g = threadIdx.x; g < elems / 4; g += kWave) {
+        uint32_t w[4 * W];
+#pragma unroll
+        for (int kg = 0; kg < W; ++kg)
+            byte_transpose4(l32[(4 * kg) * pw + g], l32[(4 * kg + 1) * pw + g],
+                            l32[(4 * kg + 2) * pw + g], l32[(4 * kg + 3) * pw + g], w[kg],
+                            w[W + kg], w[2 * W + kg], w[3 * W + kg]);
+        uint4 *d4 = reinterpret_cast<uint4 *>(out + 4 * g * E);
+#pragma unroll
+        for (int q = 0; q < W; ++q)
+            d4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+    }
+}
+
 __device__ __forceinline__ void block_forward_bytes(const uint8_t *__restrict__ in, uint8_t *lds,
                                                     int64_t elems, int64_t E)
 {
+    if (((uintptr_t)in % 16) == 0) {
+        switch (E) {
+        case 4: block_forward_bytes_fast<4>(in, lds, elems); return;
+        case 8: block_forward_bytes_fast<8>(in, lds, elems); return;
+        case 12: block_forward_bytes_fast<12>(in, lds, elems); return;
+        case 16: block_forward_bytes_fast<16>(in, lds, elems); return;
+        default: break;
+        }
+    }
     uint32_t *l32 = reinterpret_cast<uint32_t *>(lds);
     for (int64_t g = lane_id(); g < elems / 4; g += kWave) {
         const uint8_t *src = in + 4 * g * E;
@@ -159,6 +223,15 @@ __device__ __forceinline__ void block_forward_bytes(const uint8_t *__restrict__ 
 __device__ __forceinline__ void block_inverse_bytes(const uint8_t *lds, uint8_t *__restrict__ out,
                                                     int64_t elems, int64_t E)
 {
+    if (((uintptr_t)out % 16) == 0) {
+        switch (E) {
+        case 4: block_inverse_bytes_fast<4>(lds, out, elems); return;
+        case 8: block_inverse_bytes_fast<8>(lds, out, elems); return;
+        case 12: block_inverse_bytes_fast<12>(lds, out, elems); return;
+        case 16: block_inverse_bytes_fast<16>(lds, out, elems); return;
+        default: break;
+        }
+    }
     const uint32_t *l32 = reinterpret_cast<const uint32_t *>(lds);
     for (int64_t g = threadIdx.x; g < elems / 4; g += kWave) {
         uint8_t *dst = out + 4 * g * E;
