@@ -120,12 +120,72 @@ __global__ __launch_bounds__(256) void k_byteshuffle(const uint8_t *__restrict__
     reinterpret_cast<uint32_t *>(out + b * nb * E)[w] = v;
 }
 
+// The byte shuffle for element sizes that are multiples of 4, both buffers
+// 16-byte aligned: a thread takes 4 elements of a block (4E bytes, 16-byte
+// accesses) and transposes each 4 x 4 byte sub-matrix (dword kg of the 4
+// elements) in registers into dword g of planes 4kg .. 4kg + 3.
+template <int E, bool INV>
+__global__ __launch_bounds__(256) void k_byteshuffle_fast(const uint8_t *__restrict__ in,
+                                                          uint8_t *__restrict__ out,
+                                                          int64_t n_blocks, int64_t nb)
+{
+    constexpr int W = E / 4;
+    const int64_t per = nb / 4; // groups of 4 elements per block
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n_blocks * per) return;
+    const int64_t b = t / per, g = t - b * per;
+    const int64_t base = b * nb * E;
+    uint32_t w[4 * W];
+    if constexpr (!INV) {
+        const uint4 *s4 = reinterpret_cast<const uint4 *>(in + base + 4 * g * E);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const uint4 v = s4[q];
+            w[4 * q] = v.x;
+            w[4 * q + 1] = v.y;
+            w[4 * q + 2] = v.z;
+            w[4 * q + 3] = v.w;
+        }
+        uint32_t *o32 = reinterpret_cast<uint32_t *>(out + base);
+#pragma unroll
+        for (int kg = 0; kg < W; ++kg) {
+            uint32_t o0, o1, o2, o3;
+            byte_transpose4(w[kg], w[W + kg], w[2 * W + kg], w[3 * W + kg], o0, o1, o2, o3);
+            o32[(4 * kg) * per + g] = o0;
+            o32[(4 * kg + 1) * per + g] = o1;
+            o32[(4 * kg + 2) * per + g] = o2;
+            o32[(4 * kg + 3) * per + g] = o3;
+        }
+    } else {
+        const uint32_t *i32 = reinterpret_cast<const uint32_t *>(in + base);
+#pragma unroll
+        for (int kg = 0; kg < W; ++kg)
+            byte_transpose4(i32[(4 * kg) * per + g], i32[(4 * kg + 1) * per + g],
+                            i32[(4 * kg + 2) * per + g], i32[(4 * kg + 3) * per + g], w[kg],
+                            w[W + kg], w[2 * W + kg], w[3 * W + kg]);
+        uint4 *d4 = reinterpret_cast<uint4 *>(out + base + 4 * g * E);
+#pragma unroll
+        for (int q = 0; q < W; ++q)
+            d4[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+    }
+}
+
 template <bool INV>
 hipError_t bytes_launch(const uint8_t *in, uint8_t *out, int64_t n_blocks, int64_t nb, int64_t E,
                         hipStream_t s)
 {
     const int64_t words = n_blocks * nb * E / 4;
     if (words == 0) return hipSuccess;
+    if (((uintptr_t)in | (uintptr_t)out) % 16 == 0 && E % 4 == 0 && E <= 16) {
+        const unsigned grid = (unsigned)((n_blocks * (nb / 4) + 255) / 256);
+        switch (E) {
+        case 4: hipLaunchKernelGGL((k_byteshuffle_fast<4, INV>), dim3(grid), dim3(256), 0, s, in, out, n_blocks, nb); break;
+        case 8: hipLaunchKernelGGL((k_byteshuffle_fast<8, INV>), dim3(grid), dim3(256), 0, s, in, out, n_blocks, nb); break;
+        case 12: hipLaunchKernelGGL((k_byteshuffle_fast<12, INV>), dim3(grid), dim3(256), 0, s, in, out, n_blocks, nb); break;
+        default: hipLaunchKernelGGL((k_byteshuffle_fast<16, INV>), dim3(grid), dim3(256), 0, s, in, out, n_blocks, nb); break;
+        }
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_byteshuffle<INV>), dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,
                        in, out, n_blocks, nb, E);
     return hipGetLastError();

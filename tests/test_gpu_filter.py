@@ -33,7 +33,20 @@ def host(t):
 
 
 CASES = [(4, 2048, 2048 * 3 + 13), (2, 4096, 4096 * 2 + 8), (1, 8192, 8192 * 2 + 7), (8, 1024, 1024 * 5),
-         (3, 64, 999), (16, 512, 512 * 3 + 16), (4, 16384, 16384 * 2 + 100), (4, 16, 1), (4, 16, 0)]
+         (3, 64, 999), (16, 512, 512 * 3 + 16), (4, 16384, 16384 * 2 + 100), (4, 16, 1), (4, 16, 0),
+         (12, 512, 512 * 2 + 24)]
+
+
+def test_byteshuffle_unaligned_input(bsg):
+    """An input 4 bytes past a 16-byte boundary takes the byte-by-byte
+    kernel instead of the 16-byte one; both give the oracle's bytes."""
+    E, nb, n = 4, 2048, 2048 * 2 + 40
+    x = np.random.default_rng(77).integers(0, 256, n * E + 4, dtype=np.uint8)
+    d = dev(x)[4:]
+    ref = oracle.byteshuffle(x[4:].copy(), E, nb)
+    y = bsg.byteshuffle(d, E, nb)
+    assert np.array_equal(host(y), ref)
+    assert np.array_equal(host(bsg.byteunshuffle(y, E, nb)), x[4:])
 
 
 @pytest.mark.parametrize("E,nb,n", CASES)
