@@ -531,9 +531,18 @@ def bench_filters(args, torch, bsg):
                                                            filter=flt), args.steps, args.warmup)
         torch.cuda.synchronize()
         assert int(status.item()) == 0 and torch.equal(dec, r), name
+        # the filter alone (no LZ4), forward then inverse
+        fwd, inv = ((bsg.bitshuffle, bsg.bitunshuffle) if flt == bsg.BSG_FILTER_BIT
+                    else (bsg.byteshuffle, bsg.byteunshuffle))
+        f_ms = _time_calls(torch, lambda: fwd(r, 4, nb, out=dec), args.steps, args.warmup)
+        i_ms = _time_calls(torch, lambda: inv(dec, 4, nb, out=out[:U]), args.steps, args.warmup)
+        torch.cuda.synchronize()
+        assert torch.equal(out[:U], r), name
         rows[name] = {"ratio": round(m / U, 5),
                       "compress_GBps": round(U / (float(np.median(c_ms)) * 1e-3) / 1e9, 2),
-                      "decompress_GBps": round(U / (float(np.median(d_ms)) * 1e-3) / 1e9, 2)}
+                      "decompress_GBps": round(U / (float(np.median(d_ms)) * 1e-3) / 1e9, 2),
+                      "filter_only_GBps": round(U / (float(np.median(f_ms)) * 1e-3) / 1e9, 2),
+                      "inverse_only_GBps": round(U / (float(np.median(i_ms)) * 1e-3) / 1e9, 2)}
     res = {
         "metric": "uncompressed GB/s (compress & decompress) + % HBM peak; p50/p99 latency",
         "value": rows["bitshuffle"]["decompress_GBps"], "unit": "GB/s", "n_gpus": 1,
