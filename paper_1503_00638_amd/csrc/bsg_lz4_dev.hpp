@@ -664,13 +664,22 @@ __device__ __forceinline__ bool read_len_ext(const uint8_t *ci, int &ip, int ien
 // sources and writes the dword back unchanged, so the buffer has 64 dwords
 // of padding after it.  Sources may lie up to 3 bytes before b32[0], so the
 // buffer has a padding dword in front.
+//
+// A byte mask takes three vector instructions: the bytes of the dword at
+// byte d that lie at or past byte t are the low 32 bits of 0xFFFFFFFF
+// shifted left by 8 (t - d), the shift clamped to [0, 32] (one med3; the
+// 64-bit shift turns 32 into 0).
+__device__ __forceinline__ uint32_t ge_mask(int d, int t)
+{
+    int s = 8 * (t - d);
+    s = s < 0 ? 0 : (s > 32 ? 32 : s);
+    return (uint32_t)(0xFFFFFFFFull << s);
+}
+
+// The bytes of the dword at byte d inside [op, end).
 __device__ __forceinline__ uint32_t range_mask(int d, int op, int end)
 {
-    const int lo = op - d > 0 ? op - d : 0; // 0..3
-    const int e = end - d;
-    const int hi = e < 4 ? (e > 0 ? e : 0) : 4; // 0..4 (0: past the range)
-    const uint32_t mhi = hi >= 4 ? 0xFFFFFFFFu : ((1u << (8 * hi)) - 1u);
-    return mhi & ~((1u << (8 * lo)) - 1u);
+    return ge_mask(d, op) & ~ge_mask(d, end);
 }
 
 // (every lane reads its destination dword together with its sources, so a
@@ -688,7 +697,7 @@ __device__ __forceinline__ void put_word(uint32_t *b32, int w, uint32_t v, uint3
 __device__ __forceinline__ void dcopy_step(uint32_t *b32, int w, int delta, uint32_t sh, int op,
                                            int end)
 {
-    const int a = (4 * w + delta) >> 2;
+    const int a = w + (delta >> 2); // (4 w + delta) >> 2, no masking
     const uint32_t old = b32[w];
     put_word(b32, w, __builtin_amdgcn_alignbyte(b32[a + 1], b32[a], sh), old, op, end);
 }
@@ -710,21 +719,21 @@ __device__ __forceinline__ void dcopy(uint32_t *b32, int op, int src, int len)
 // whose source ends at or before a: d1 = -off, off >= b - a) and
 // out[b, c) = buf[b + d2, c + d2) (literals, d2 >= 0).  Both are
 // independent of each other's output, so each lane builds its dword from
-// both sources: the match bytes under the mask of [a, b), the literal bytes
-// under the rest of the mask of [a, c) (both masks are valid for every dword
-// from a / 4 on, so no lane branches).  Same padding and ordering rules as
-// dcopy.
+// both sources and its old value with three byte masks (bytes from a, from
+// b and from c on): old below a, match bytes in [a, b), literal bytes in
+// [b, c), old from c on.  The masks are valid for every dword, so no lane
+// branches.  Same padding and ordering rules as dcopy.
 __device__ __forceinline__ void dcopy2_step(uint32_t *b32, int w, int d1, uint32_t sh1, int d2,
                                             uint32_t sh2, int a, int b, int c)
 {
     const uint32_t old = b32[w];
-    const int s1 = (4 * w + d1) >> 2, s2 = (4 * w + d2) >> 2;
+    const int s1 = w + (d1 >> 2), s2 = w + (d2 >> 2); // (4 w + d) >> 2
     const uint32_t v1 = __builtin_amdgcn_alignbyte(b32[s1 + 1], b32[s1], sh1);
     const uint32_t v2 = __builtin_amdgcn_alignbyte(b32[s2 + 1], b32[s2], sh2);
-    const uint32_t m1 = range_mask(4 * w, a, b);
-    const uint32_t mall = range_mask(4 * w, a, c);
-    const uint32_t v = (v1 & m1) | (v2 & ~m1);
-    b32[w] = (v & mall) | (old & ~mall);
+    const uint32_t gb = ge_mask(4 * w, b), gc = ge_mask(4 * w, c), ga = ge_mask(4 * w, a);
+    const uint32_t t = (v2 & gb) | (v1 & ~gb); // from b on the literals, below it the match
+    const uint32_t u = (old & gc) | (t & ~gc); // from c on unchanged
+    b32[w] = (u & ga) | (old & ~ga);           // below a unchanged
 }
 
 __device__ __forceinline__ void dcopy2(uint32_t *b32, int a, int d1, int b, int d2, int c)
@@ -767,8 +776,9 @@ __device__ __forceinline__ void dmatch_step(uint32_t *b32, int w, int r, int off
     const int sidx = base + r;
     uint32_t v = __builtin_amdgcn_alignbyte(b32[(sidx >> 2) + 1], b32[sidx >> 2],
                                             (uint32_t)(sidx & 3));
-    const int k = off - r;
-    if (k < 4) v = (v & ((1u << (8 * k)) - 1u)) | (head << (8 * k));
+    const int k = off - r; // bytes from k on (none when k >= 4) wrap to the period's start
+    const uint32_t gk = ge_mask(0, k);
+    v = (v & ~gk) | ((head << (8 * (k & 3))) & gk);
     put_word(b32, w, v, old, op, end);
 }
 
