@@ -407,6 +407,42 @@ def test_decode_long_overlapping_periods(bsg):
         assert np.array_equal(got, expect)
 
 
+def test_decode_offsets_from_256_in_8k_blocks(bsg):
+    """Overlapping matches at offsets on both sides of 256 bytes (the output
+    of one 64-lane copy step) in the 8 KiB blocks of the hot path, every
+    byte phase of the period start, some periods broken by a changed byte,
+    encoded by the oracle and, when present, by the system liblz4."""
+    E, nb = 4, 2048
+    rng = np.random.default_rng(23)
+    periods = [255, 256, 257, 258, 259, 300, 511, 512, 513, 1024, 2047, 4096]
+    blocks = []
+    for k, p in enumerate(periods):
+        lead = k % 4
+        pat = rng.integers(0, 256, p, dtype=np.uint8)
+        body = np.resize(pat, nb * E - lead)
+        if k % 3 == 2:  # a changed byte ends one match and starts another
+            body[int(rng.integers(p, body.size))] ^= 0x5A
+        blocks.append(rng.integers(0, 256, lead, dtype=np.uint8).tobytes() + body.tobytes())
+    nblk = len(blocks)
+    data_sh = b"".join(blocks)
+    expect = oracle.bitunshuffle(np.frombuffer(data_sh, np.uint8), E, nb)
+    encoders = [lambda b: oracle.lz4_compress_block(np.frombuffer(b, np.uint8))]
+    if lz4ref.available():
+        encoders += [lz4ref.compress_default, lz4ref.compress_hc]
+    for enc in encoders:
+        pays = [enc(b) for b in blocks]
+        assert any(q[1] is not None and q[1] >= 256 and q[2] > q[1]
+                   for pay in pays for q in lz4ref.parse_sequences(pay))
+        off = np.zeros(nblk + 1, dtype=np.uint64)
+        off[1:] = np.cumsum([len(q) for q in pays])
+        hdr = np.array([0x31475342, E], dtype=np.uint32).tobytes() + \
+            np.array([nblk * nb], dtype=np.uint64).tobytes() + \
+            np.array([nb, nblk], dtype=np.uint32).tobytes()
+        stream = np.frombuffer(hdr + off.tobytes() + b"".join(pays), dtype=np.uint8)
+        got = host(bsg.decompress_sync(dev(stream), nblk * nb, E, nb))
+        assert np.array_equal(got, expect)
+
+
 def test_decode_rejects_corruption(bsg):
     E, nb = 4, 2048
     x = synth.gen_gauss_int32(2048 * 8 + 5, 6, 2)
