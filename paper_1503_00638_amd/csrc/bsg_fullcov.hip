@@ -64,8 +64,7 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
     // the LDS banks); the factorisation reads column k from its copy colk
     const int LD = D + (D & 1);
     double *Q = smem;
-    double *Mdiag = Q + D * LD;           // D
-    double *colk = Mdiag + D;             // D: column k of L during step k
+    double *colk = Q + D * LD;            // D: column k of L during step k
     Cplx *V = reinterpret_cast<Cplx *>(colk + D); // I x I
     int *dof = reinterpret_cast<int *>(V + I * I);  // D: product * 2 + (Im ? 1 : 0)
     __shared__ int bad;
@@ -133,14 +132,15 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
             break;
         }
         const double lkk = sqrt(d);
-        __syncthreads(); // everyone has read Q[k][k]
-        if (tid == 0) Q[k * LD + k] = lkk;
         for (int i = k + 1 + tid; i < D; i += blockDim.x) {
             const double lik = Q[i * LD + k] / lkk;
             Q[i * LD + k] = lik;
             colk[i] = lik;
         }
         __syncthreads();
+        // every thread has read Q[k][k] before the barrier, and the trailing
+        // update below does not touch it
+        if (tid == 0) Q[k * LD + k] = lkk;
         // trailing lower triangle, rows and columns k+1 .. D-1, on a 16 x 16
         // grid of threads
         for (int i = k + 1 + (tid >> 4); i < D; i += 16) {
@@ -159,7 +159,10 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
     if (!failed) {
         for (int j = tid; j < D; j += blockDim.x) {
             const double mjj = 1.0 / Q[j * LD + j];
-            Mdiag[j] = mjj;
+            // (Q^-1)_jj = sum_{i >= j} M_ij^2 in increasing i, added as each
+            // M_ij is formed (its own chain, beside the next row's sum)
+            double q = 0.0;
+            q = q + mjj * mjj;
             for (int i = j + 1; i < D; ++i) {
                 double acc = Q[i * LD + j] * mjj;
                 // (unrolled so that the loads of later terms issue ahead;
@@ -168,12 +171,8 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
                 for (int m = j + 1; m < i; ++m) acc = acc + Q[i * LD + m] * Q[j * LD + m];
                 const double mij = -acc / Q[i * LD + i];
                 Q[j * LD + i] = mij;
+                q = q + mij * mij;
             }
-            // (Q^-1)_jj = sum_{i >= j} M_ij^2 in increasing i
-            double q = 0.0;
-            q = q + mjj * mjj;
-#pragma unroll 8
-            for (int i = j + 1; i < D; ++i) q = q + Q[j * LD + i] * Q[j * LD + i];
             if (j == tid) qk = q;
             if (a.qdiag) a.qdiag[s * D + j] = q;
         }
@@ -207,7 +206,7 @@ hipError_t launch_fullcov(const float *vis, const float *autos, int64_t F, int64
     if (F * T == 0 || D == 0) return hipSuccess;
     FullcovArgs a{reinterpret_cast<const float2 *>(vis), autos, F, T, (int)I, P, D, c,
                   reinterpret_cast<float2 *>(vis_out), qdiag};
-    const size_t lds = sizeof(double) * ((size_t)D * (D + (D & 1)) + 2 * D) +
+    const size_t lds = sizeof(double) * ((size_t)D * (D + (D & 1)) + D) +
                        sizeof(Cplx) * (size_t)(I * I) +
                        sizeof(int) * (size_t)D;
     hipLaunchKernelGGL(k_fullcov, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
