@@ -271,6 +271,23 @@ __device__ __forceinline__ void stage_block(const uint8_t *__restrict__ src, int
     }
 }
 
+// Elements of a full block of MAXB bytes for a register-path element class
+// (the default block: MAXB / E rounded down to a multiple of 8), or 0 where
+// the class has no register path or the block is not whole units.  With
+// the count a constant the plane stride is one too, and every LDS read of
+// the decoder's inverse transpose takes an immediate offset (pairs of plane
+// words per instruction).  (Not for 16-byte elements, whose decoders would
+// need more registers for it.)
+template <int MAXB, int EC> constexpr int64_t full_block_elems()
+{
+    if constexpr (EC == 1 || EC == 2 || EC == 4 || EC == 8) {
+        constexpr int64_t n = (MAXB / EC) / 8 * 8;
+        return n % Unit<EC>::G == 0 ? n : 0;
+    } else {
+        return 0;
+    }
+}
+
 // ---- LZ4 emission, one sequence per lane ------------------------------------
 // Exclusive prefix sum of x over the wave's lanes; total = the sum of all.
 // Inclusive sums within rows of 16 lanes by shifts of 1, 2, 4 and 8, then
@@ -1134,7 +1151,18 @@ __device__ __forceinline__ bool decode_one(const uint8_t *__restrict__ payload, 
     const bool ok = decode_inplace(B, base, base + len, ob);
     __builtin_amdgcn_s_setprio(0);
     wave_sync();
-    if (ok) unstage_block<EC>(reinterpret_cast<const uint8_t *>(B), elems, E, dst, fast_out);
+    if (ok) {
+        constexpr int64_t kFull = full_block_elems<MAXB, EC>();
+        bool done = false;
+        if constexpr (kFull != 0) {
+            if (fast_out && elems == kFull) {
+                unstage_fast<EC>(reinterpret_cast<const uint8_t *>(B), kFull, dst);
+                done = true;
+            }
+        }
+        if (!done)
+            unstage_block<EC>(reinterpret_cast<const uint8_t *>(B), elems, E, dst, fast_out);
+    }
     wave_sync();
     return ok;
 }

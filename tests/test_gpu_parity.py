@@ -66,6 +66,13 @@ def test_round_special_values(bsg):
         ref = oracle.round_to_noise(vis, autos, N, f)
         got = host(bsg.round_to_noise(dev(vis), dev(autos), N, f))
         assert np.array_equal(u32(got), u32(ref)), f
+        # the same rounding fused into the encoder's staging: 2048-element
+        # blocks take the 16-visibility register path where a unit stays in
+        # one product, the per-visibility path where it crosses one, and the
+        # ragged last block the generic path
+        fused, nb = bsg.round_compress(dev(vis), dev(autos), N, f, block_size=2048)
+        m = int(host(nb)[0])
+        assert np.array_equal(host(fused)[:m], oracle.compress(ref, 4, 2048)), f
 
 
 def ties_at_binade_inputs():
