@@ -250,15 +250,24 @@ class Server:
         return []
 
     def _collect(self, fl, keep, kept):
-        """Copies of the kept requests' results (tests and sampled checks)
-        before the arena regions are reused."""
+        """Copies of the kept requests' results (tests and sampled checks).
+        They are made on the batch's own stream, so that the slot's next
+        batch cannot overwrite its length and status words first, and they
+        are finished before the arena regions are freed: a freed region may
+        be handed at once to a batch on another stream."""
         comp = [r for r in fl.reqs if r.op == "compress"]
         decs = [r for r in fl.reqs if r.op == "decompress"]
-        for lst, word in ((comp, fl.slot.nbytes), (decs, fl.slot.status)):
-            for k, r in enumerate(lst):
-                if r.rid in keep:
-                    reg = fl.outs[r.rid]
-                    kept[r.rid] = (self.arena.view(reg, reg[1]).clone(), word[k:k + 1].clone())
+        copied = False
+        with torch.cuda.stream(fl.slot.stream):
+            for lst, word in ((comp, fl.slot.nbytes), (decs, fl.slot.status)):
+                for k, r in enumerate(lst):
+                    if r.rid in keep:
+                        reg = fl.outs[r.rid]
+                        kept[r.rid] = (self.arena.view(reg, reg[1]).clone(),
+                                       word[k:k + 1].clone())
+                        copied = True
+        if copied:
+            fl.slot.stream.synchronize()
 
     def run(self, requests, mode: str = "batch", keep=()):
         """Serve `requests` (sorted by arrival) in real time.  mode 'batch'
