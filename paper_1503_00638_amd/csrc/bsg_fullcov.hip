@@ -67,6 +67,7 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
     double *colk = Q + D * LD;            // D: column k of L during step k
     Cplx *V = reinterpret_cast<Cplx *>(colk + D); // I x I
     int *dof = reinterpret_cast<int *>(V + I * I);  // D: product * 2 + (Im ? 1 : 0)
+    int *dij = dof + D;                             // D: the product's inputs, i | j << 8
     __shared__ int bad;
     const int tid = threadIdx.x;
     const int64_t s = blockIdx.x; // sample (fr, t)
@@ -78,8 +79,12 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
         for (int p = 0; p < P; ++p) {
             int i, j;
             pair_of(I, p, i, j);
+            dij[k] = i | j << 8;
             dof[k++] = 2 * p;
-            if (i != j) dof[k++] = 2 * p + 1;
+            if (i != j) {
+                dij[k] = i | j << 8;
+                dof[k++] = 2 * p + 1;
+            }
         }
     }
     for (int e = tid; e < I * I; e += blockDim.x) {
@@ -99,12 +104,11 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
     }
     __syncthreads();
 
-    // Q = 2N C (Eqs. rad_full1-3)
+    // Q = 2N C (Eqs. rad_full1-3); each degree of freedom's inputs come from
+    // the table built above
     for (int e = tid; e < D * D; e += blockDim.x) {
         const int x = e / D, y = e - x * D;
-        int i, j, g, h;
-        pair_of(I, dof[x] >> 1, i, j);
-        pair_of(I, dof[y] >> 1, g, h);
+        const int i = dij[x] & 255, j = dij[x] >> 8, g = dij[y] & 255, h = dij[y] >> 8;
         const bool ix = dof[x] & 1, iy = dof[y] & 1;
         const Cplx A = mul_conj(V[i * I + g], V[j * I + h]);
         const Cplx B = mul_conj(V[i * I + h], V[j * I + g]);
@@ -131,7 +135,10 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
             if (tid == 0) bad = 1;
             break;
         }
-        const double lkk = sqrt(d);
+        // (only the threads that scale the column, and thread 0, need L_kk:
+        // a wave with none of them skips the square root)
+        double lkk = 0.0;
+        if (k + 1 + tid < D || tid == 0) lkk = sqrt(d);
         for (int i = k + 1 + tid; i < D; i += blockDim.x) {
             const double lik = Q[i * LD + k] / lkk;
             Q[i * LD + k] = lik;
@@ -208,7 +215,7 @@ hipError_t launch_fullcov(const float *vis, const float *autos, int64_t F, int64
                   reinterpret_cast<float2 *>(vis_out), qdiag};
     const size_t lds = sizeof(double) * ((size_t)D * (D + (D & 1)) + D) +
                        sizeof(Cplx) * (size_t)(I * I) +
-                       sizeof(int) * (size_t)D;
+                       sizeof(int) * (size_t)(2 * D);
     hipLaunchKernelGGL(k_fullcov, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
     return hipGetLastError();
 }
