@@ -682,10 +682,10 @@ __device__ __forceinline__ bool read_len_ext(const uint8_t *ci, int &ip, int ien
 // of padding after it.  Sources may lie up to 3 bytes before b32[0], so the
 // buffer has a padding dword in front.
 //
-// A byte mask takes three vector instructions: the bytes of the dword at
-// byte d that lie at or past byte t are the low 32 bits of 0xFFFFFFFF
-// shifted left by 8 (t - d), the shift clamped to [0, 32] (one med3; the
-// 64-bit shift turns 32 into 0).
+// A byte mask takes three or four vector instructions: the bytes of the
+// dword at byte d that lie at or past byte t are the low 32 bits of
+// 0xFFFFFFFF shifted left by 8 (t - d), the shift clamped to [0, 32] (one
+// med3; the 64-bit shift turns 32 into 0).
 __device__ __forceinline__ uint32_t ge_mask(int d, int t)
 {
     int s = 8 * (t - d);
