@@ -24,6 +24,7 @@ namespace bsg {
 namespace {
 
 constexpr int kMaxInputs = 11; // D = 121 degrees of freedom, 120 KiB of LDS
+static_assert(kMaxInputs * kMaxInputs <= 128, "the trailing update keeps 8 columns per thread");
 
 struct Cplx {
     double re, im;
@@ -149,12 +150,20 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
         // update below does not touch it
         if (tid == 0) Q[k * LD + k] = lkk;
         // trailing lower triangle, rows and columns k+1 .. D-1, on a 16 x 16
-        // grid of threads
+        // grid of threads; a thread's columns j0 + 16 b are the same for all
+        // its rows, so their column-k values stay in registers (D <= 128)
+        const int j0 = k + 1 + (tid & 15);
+        double cj[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) cj[b] = j0 + 16 * b < D ? colk[j0 + 16 * b] : 0.0;
         for (int i = k + 1 + (tid >> 4); i < D; i += 16) {
             const double lik = colk[i];
-#pragma unroll 4
-            for (int j = k + 1 + (tid & 15); j <= i; j += 16)
-                Q[i * LD + j] = Q[i * LD + j] - lik * colk[j];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const int j = j0 + 16 * b;
+                if (j > i) break;
+                Q[i * LD + j] = Q[i * LD + j] - lik * cj[b];
+            }
         }
         __syncthreads();
     }
