@@ -25,6 +25,9 @@ namespace {
 
 constexpr int kMaxInputs = 11; // D = 121 degrees of freedom, 120 KiB of LDS
 static_assert(kMaxInputs * kMaxInputs <= 128, "the trailing update keeps 8 columns per thread");
+// The inverse forms four rows per pass (the instance FOUR) up to this many
+// degrees of freedom (8 inputs); above it the one-row instance was faster.
+constexpr int kFourRowMaxD = 64;
 
 struct Cplx {
     double re, im;
@@ -56,6 +59,7 @@ struct FullcovArgs {
     double *qdiag;    // [F][T][D] or nullptr
 };
 
+template <bool FOUR>
 __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
 {
     extern __shared__ double smem[];
@@ -179,12 +183,46 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
             // M_ij is formed (its own chain, beside the next row's sum)
             double q = 0.0;
             q = q + mjj * mjj;
-            for (int i = j + 1; i < D; ++i) {
+            const double *Mj = Q + j * LD; // M_mj at Mj[m]
+            int i = j + 1;
+            // four rows per pass (FOUR): their sums share the terms m < i, so
+            // each M_mj is read once for the four, and the four sums are
+            // independent chains; every sum still adds its terms one by one
+            // in increasing m
+            for (; FOUR && i + 3 < D; i += 4) {
+                const double *L0 = Q + i * LD, *L1 = L0 + LD, *L2 = L1 + LD, *L3 = L2 + LD;
+                double a0 = L0[j] * mjj, a1 = L1[j] * mjj, a2 = L2[j] * mjj, a3 = L3[j] * mjj;
+#pragma unroll 4
+                for (int m = j + 1; m < i; ++m) {
+                    const double mm = Mj[m];
+                    a0 = a0 + L0[m] * mm;
+                    a1 = a1 + L1[m] * mm;
+                    a2 = a2 + L2[m] * mm;
+                    a3 = a3 + L3[m] * mm;
+                }
+                const double m0 = -a0 / L0[i];
+                Q[j * LD + i] = m0;
+                q = q + m0 * m0;
+                a1 = a1 + L1[i] * m0;
+                a2 = a2 + L2[i] * m0;
+                a3 = a3 + L3[i] * m0;
+                const double m1 = -a1 / L1[i + 1];
+                Q[j * LD + i + 1] = m1;
+                q = q + m1 * m1;
+                a2 = a2 + L2[i + 1] * m1;
+                a3 = a3 + L3[i + 1] * m1;
+                const double m2 = -a2 / L2[i + 2];
+                Q[j * LD + i + 2] = m2;
+                q = q + m2 * m2;
+                a3 = a3 + L3[i + 2] * m2;
+                const double m3 = -a3 / L3[i + 3];
+                Q[j * LD + i + 3] = m3;
+                q = q + m3 * m3;
+            }
+            for (; i < D; ++i) {
                 double acc = Q[i * LD + j] * mjj;
-                // (unrolled so that the loads of later terms issue ahead;
-                // the terms are still added one by one, in order)
 #pragma unroll 8
-                for (int m = j + 1; m < i; ++m) acc = acc + Q[i * LD + m] * Q[j * LD + m];
+                for (int m = j + 1; m < i; ++m) acc = acc + Q[i * LD + m] * Mj[m];
                 const double mij = -acc / Q[i * LD + i];
                 Q[j * LD + i] = mij;
                 q = q + mij * mij;
@@ -225,7 +263,10 @@ hipError_t launch_fullcov(const float *vis, const float *autos, int64_t F, int64
     const size_t lds = sizeof(double) * ((size_t)D * (D + (D & 1)) + D) +
                        sizeof(Cplx) * (size_t)(I * I) +
                        sizeof(int) * (size_t)(2 * D);
-    hipLaunchKernelGGL(k_fullcov, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
+    if (D <= kFourRowMaxD)
+        hipLaunchKernelGGL(k_fullcov<true>, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_fullcov<false>, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
