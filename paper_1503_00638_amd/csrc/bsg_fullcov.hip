@@ -25,8 +25,8 @@ namespace {
 
 constexpr int kMaxInputs = 11; // D = 121 degrees of freedom, 120 KiB of LDS
 static_assert(kMaxInputs * kMaxInputs <= 128, "the trailing update keeps 8 columns per thread");
-// The inverse forms four rows per pass (the instance FOUR) up to this many
-// degrees of freedom (8 inputs); above it the one-row instance was faster.
+// The inverse forms ROWS rows of a column per pass: 4 up to this many
+// degrees of freedom (8 inputs), 2 above it, where 4 was slower.
 constexpr int kFourRowMaxD = 64;
 
 struct Cplx {
@@ -59,7 +59,7 @@ struct FullcovArgs {
     double *qdiag;    // [F][T][D] or nullptr
 };
 
-template <bool FOUR>
+template <int ROWS>
 __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
 {
     extern __shared__ double smem[];
@@ -185,39 +185,31 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
             q = q + mjj * mjj;
             const double *Mj = Q + j * LD; // M_mj at Mj[m]
             int i = j + 1;
-            // four rows per pass (FOUR): their sums share the terms m < i, so
-            // each M_mj is read once for the four, and the four sums are
-            // independent chains; every sum still adds its terms one by one
-            // in increasing m
-            for (; FOUR && i + 3 < D; i += 4) {
-                const double *L0 = Q + i * LD, *L1 = L0 + LD, *L2 = L1 + LD, *L3 = L2 + LD;
-                double a0 = L0[j] * mjj, a1 = L1[j] * mjj, a2 = L2[j] * mjj, a3 = L3[j] * mjj;
+            // ROWS rows per pass: their sums share the terms m < i, so each
+            // M_mj is read once for all of them, and the sums are independent
+            // chains; every sum still adds its terms one by one in increasing m
+            for (; ROWS > 1 && i + ROWS - 1 < D; i += ROWS) {
+                const double *Lr[ROWS];
+                double acc[ROWS], mv[ROWS];
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+                    Lr[r] = Q + (i + r) * LD;
+                    acc[r] = Lr[r][j] * mjj;
+                }
 #pragma unroll 4
                 for (int m = j + 1; m < i; ++m) {
                     const double mm = Mj[m];
-                    a0 = a0 + L0[m] * mm;
-                    a1 = a1 + L1[m] * mm;
-                    a2 = a2 + L2[m] * mm;
-                    a3 = a3 + L3[m] * mm;
+#pragma unroll
+                    for (int r = 0; r < ROWS; ++r) acc[r] = acc[r] + Lr[r][m] * mm;
                 }
-                const double m0 = -a0 / L0[i];
-                Q[j * LD + i] = m0;
-                q = q + m0 * m0;
-                a1 = a1 + L1[i] * m0;
-                a2 = a2 + L2[i] * m0;
-                a3 = a3 + L3[i] * m0;
-                const double m1 = -a1 / L1[i + 1];
-                Q[j * LD + i + 1] = m1;
-                q = q + m1 * m1;
-                a2 = a2 + L2[i + 1] * m1;
-                a3 = a3 + L3[i + 1] * m1;
-                const double m2 = -a2 / L2[i + 2];
-                Q[j * LD + i + 2] = m2;
-                q = q + m2 * m2;
-                a3 = a3 + L3[i + 2] * m2;
-                const double m3 = -a3 / L3[i + 3];
-                Q[j * LD + i + 3] = m3;
-                q = q + m3 * m3;
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+                    for (int t = 0; t < r; ++t) acc[r] = acc[r] + Lr[r][i + t] * mv[t];
+                    mv[r] = -acc[r] / Lr[r][i + r];
+                    Q[j * LD + i + r] = mv[r];
+                    q = q + mv[r] * mv[r];
+                }
             }
             for (; i < D; ++i) {
                 double acc = Q[i * LD + j] * mjj;
@@ -264,9 +256,9 @@ hipError_t launch_fullcov(const float *vis, const float *autos, int64_t F, int64
                        sizeof(Cplx) * (size_t)(I * I) +
                        sizeof(int) * (size_t)(2 * D);
     if (D <= kFourRowMaxD)
-        hipLaunchKernelGGL(k_fullcov<true>, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(k_fullcov<4>, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
     else
-        hipLaunchKernelGGL(k_fullcov<false>, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(k_fullcov<2>, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
