@@ -6,11 +6,12 @@
 // G2 = 12 f s_k^2.  With Q = 2N C this is G2 = c / (Q^-1)_kk, c = (12 f)/(2N).
 //
 // One workgroup per sample holds Q in LDS (D = I^2 <= 121, so at most
-// 120 KiB): the Hermitian V of the sample, Q from it, a right-looking
-// Cholesky factorisation Q = L L^T in place (a step per column, the
-// trailing update spread over the workgroup), then M = L^-1 one column per
-// thread (stored transposed in the free upper triangle) and
-// (Q^-1)_kk = sum_i M_ik^2.  Every element sees its operations in the same
+// 120 KiB): the Hermitian V of the sample, the lower triangle of Q from it,
+// a right-looking Cholesky factorisation Q = L L^T in place (a step per
+// column, the trailing update spread over the workgroup), then M = L^-1 one
+// column per thread, a few rows per pass (stored transposed in the free
+// upper triangle) and (Q^-1)_kk = sum_i M_ik^2.  Every element sees its
+// operations in the same
 // order as a plain serial implementation (sums in increasing index order),
 // so the results are reproducible bit for bit.  A sample whose Q is not
 // positive definite gets no estimate and is left unchanged.
@@ -109,10 +110,16 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
     }
     __syncthreads();
 
-    // Q = 2N C (Eqs. rad_full1-3); each degree of freedom's inputs come from
-    // the table built above
-    for (int e = tid; e < D * D; e += blockDim.x) {
-        const int x = e / D, y = e - x * D;
+    // Q = 2N C (Eqs. rad_full1-3), its lower triangle only (the factorisation
+    // reads nothing else, and the inverse writes the upper half before it
+    // reads it); element e of the triangle in row-major order is (x, y),
+    // y <= x, from a float estimate of the row corrected by exact checks.
+    // Each degree of freedom's inputs come from the table built above.
+    for (int e = tid; e < D * (D + 1) / 2; e += blockDim.x) {
+        int x = (int)((__builtin_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+        while (x * (x + 1) / 2 > e) --x;
+        while ((x + 1) * (x + 2) / 2 <= e) ++x;
+        const int y = e - x * (x + 1) / 2;
         const int i = dij[x] & 255, j = dij[x] >> 8, g = dij[y] & 255, h = dij[y] >> 8;
         const bool ix = dof[x] & 1, iy = dof[y] & 1;
         const Cplx A = mul_conj(V[i * I + g], V[j * I + h]);
