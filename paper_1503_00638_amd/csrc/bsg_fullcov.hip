@@ -11,10 +11,10 @@
 // column, the trailing update spread over the workgroup), then M = L^-1 one
 // column per thread, a few rows per pass (stored transposed in the free
 // upper triangle) and (Q^-1)_kk = sum_i M_ik^2.  Every element sees its
-// operations in the same
-// order as a plain serial implementation (sums in increasing index order),
-// so the results are reproducible bit for bit.  A sample whose Q is not
-// positive definite gets no estimate and is left unchanged.
+// operations in the same order as a plain serial implementation (sums in
+// increasing index order), so the results are reproducible bit for bit.  A
+// sample whose Q is not positive definite gets no estimate and is left
+// unchanged.
 #include <cmath>
 
 #include "bsg_internal.hpp"
