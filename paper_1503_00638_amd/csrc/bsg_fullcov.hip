@@ -26,8 +26,10 @@ namespace {
 
 constexpr int kMaxInputs = 11; // D = 121 degrees of freedom, 120 KiB of LDS
 static_assert(kMaxInputs * kMaxInputs <= 128, "the trailing update keeps 8 columns per thread");
-// The inverse forms ROWS rows of a column per pass: 4 up to this many
-// degrees of freedom (8 inputs), 2 above it, where 4 was slower.
+// Up to this many degrees of freedom (8 inputs, four samples per CU) the
+// instance has 256 threads and its inverse forms ROWS = 4 rows of a column
+// per pass; above it (one sample per CU) 512 threads hide more latency in
+// the factorisation, and 2 rows per pass were faster than 4.
 constexpr int kFourRowMaxD = 64;
 
 struct Cplx {
@@ -60,8 +62,8 @@ struct FullcovArgs {
     double *qdiag;    // [F][T][D] or nullptr
 };
 
-template <int ROWS>
-__global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
+template <int ROWS, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_fullcov(FullcovArgs a)
 {
     extern __shared__ double smem[];
     const int D = a.D, I = a.I, P = a.P;
@@ -160,14 +162,15 @@ __global__ __launch_bounds__(256) void k_fullcov(FullcovArgs a)
         // every thread has read Q[k][k] before the barrier, and the trailing
         // update below does not touch it
         if (tid == 0) Q[k * LD + k] = lkk;
-        // trailing lower triangle, rows and columns k+1 .. D-1, on a 16 x 16
-        // grid of threads; a thread's columns j0 + 16 b are the same for all
-        // its rows, so their column-k values stay in registers (D <= 128)
+        // trailing lower triangle, rows and columns k+1 .. D-1, on a
+        // (THREADS / 16) x 16 grid of threads; a thread's columns j0 + 16 b
+        // are the same for all its rows, so their column-k values stay in
+        // registers (D <= 128)
         const int j0 = k + 1 + (tid & 15);
         double cj[8];
 #pragma unroll
         for (int b = 0; b < 8; ++b) cj[b] = j0 + 16 * b < D ? colk[j0 + 16 * b] : 0.0;
-        for (int i = k + 1 + (tid >> 4); i < D; i += 16) {
+        for (int i = k + 1 + (tid >> 4); i < D; i += THREADS / 16) {
             const double lik = colk[i];
 #pragma unroll
             for (int b = 0; b < 8; ++b) {
@@ -263,9 +266,9 @@ hipError_t launch_fullcov(const float *vis, const float *autos, int64_t F, int64
                        sizeof(Cplx) * (size_t)(I * I) +
                        sizeof(int) * (size_t)(2 * D);
     if (D <= kFourRowMaxD)
-        hipLaunchKernelGGL(k_fullcov<4>, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_fullcov<4, 256>), dim3((unsigned)(F * T)), dim3(256), lds, s, a);
     else
-        hipLaunchKernelGGL(k_fullcov<2>, dim3((unsigned)(F * T)), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_fullcov<2, 512>), dim3((unsigned)(F * T)), dim3(512), lds, s, a);
     return hipGetLastError();
 }
 
