@@ -27,9 +27,10 @@ namespace {
 constexpr int kMaxInputs = 11; // D = 121 degrees of freedom, 120 KiB of LDS
 static_assert(kMaxInputs * kMaxInputs <= 128, "the trailing update keeps 8 columns per thread");
 // Up to this many degrees of freedom (8 inputs, four samples per CU) the
-// instance has 256 threads and its inverse forms ROWS = 4 rows of a column
-// per pass; above it (one sample per CU) 512 threads hide more latency in
-// the factorisation, and 2 rows per pass were faster than 4.
+// instance has 256 threads and its inverse forms ROWS = 8 rows of a column
+// per pass (16 would cost occupancy); above it (one sample per CU) 512
+// threads hide more latency in the factorisation, and 2 rows per pass were
+// faster than 4.
 constexpr int kFourRowMaxD = 64;
 
 struct Cplx {
@@ -266,7 +267,7 @@ hipError_t launch_fullcov(const float *vis, const float *autos, int64_t F, int64
                        sizeof(Cplx) * (size_t)(I * I) +
                        sizeof(int) * (size_t)(2 * D);
     if (D <= kFourRowMaxD)
-        hipLaunchKernelGGL((k_fullcov<4, 256>), dim3((unsigned)(F * T)), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_fullcov<8, 256>), dim3((unsigned)(F * T)), dim3(256), lds, s, a);
     else
         hipLaunchKernelGGL((k_fullcov<2, 512>), dim3((unsigned)(F * T)), dim3(512), lds, s, a);
     return hipGetLastError();
